@@ -1,0 +1,156 @@
+/*
+ * ffst.h -- C ABI of the MI355X (gfx950) Fast Finite Shearlet Transform.
+ *
+ * The library computes the finite discrete shearlet transform of the paper
+ * "Fast Finite Shearlet Transform: a tutorial" (Haeuser, Steidl):
+ *
+ *   forward  (eq. shearletTransform, Sec. 3.1):
+ *       c_i = ifft2( Psi_i .* fft2(f) ),            i = 0 .. eta-1
+ *   adjoint  (eq. inverseShearletTransform, Sec. 3.3):
+ *       f   = ifft2( sum_i conj(Psi_i) .* fft2(c_i) )
+ *   inverse  = adjoint, because the system is a Parseval frame
+ *       (Theorem in Sec. 3.2; Sec. 3.3).
+ *
+ * fft2 is the unnormalised 2-D DFT with kernel exp(-2 pi i ...); ifft2 carries
+ * the factor 1/(M N). Psi_i are the band-limited Meyer-type shearlet spectra
+ * (low-pass, every scale j < J and shear k of both cones, and the glued seam
+ * elements), evaluated on the grid of Sec. 3.5.1 and made even on the grid by
+ * the Nyquist-line fix of Sec. 3.8.1, so every coefficient is real.
+ *
+ * Layouts (all row-major, float32, contiguous, on the plan's device):
+ *   image         f       [batch][M][N]         rows carry omega_2, columns omega_1
+ *   coefficients  coeffs  [batch][eta][M][N]    i ordered as in Sec. 3.5.2, i = 0
+ *                                               is the low-pass (the paper counts
+ *                                               from 1); eta = 2^(J+2) - 3
+ *   spectra       Psi     [eta][M][N/2+1]       natural DFT order (no fftshift);
+ *                                               columns 0 .. N/2 of each plane,
+ *                                               the rest follows from evenness
+ *
+ * Supported on the GPU: M and N powers of two in [8, 4096]; 1 <= J <= 10.
+ *
+ * Ownership: the plan owns the spectra and its tables and frees them in
+ * ffst_destroy. The caller owns f, coeffs and the workspace ws (device memory
+ * of at least ffst_workspace_size(plan, batch) bytes, 256-byte aligned).
+ * Transform calls are asynchronous on the given HIP stream (a hipStream_t
+ * passed as void*, NULL = the default stream); they never synchronise the
+ * host and never allocate. f and coeffs must not overlap; ws must not overlap
+ * either. Two calls that run concurrently need separate workspaces.
+ *
+ * Errors: every function returns an ffst_status. Arguments are checked
+ * before any device work; on failure nothing is launched and nothing is
+ * written. ffst_last_error() returns a message for the last failure of the
+ * calling thread. No C++ exception crosses this interface.
+ */
+#ifndef FFST_H
+#define FFST_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffst_plan ffst_plan;
+
+typedef enum {
+    FFST_OK = 0,
+    FFST_EINVAL = 1,        /* bad argument (size, pointer, batch, option) */
+    FFST_EUNSUPPORTED = 2,  /* valid for the transform, not for this GPU path */
+    FFST_ENOMEM = 3,        /* device allocation failed (plan creation only) */
+    FFST_EDEVICE = 4,       /* a HIP call or kernel launch failed */
+    FFST_EBADPLAN = 5       /* NULL or destroyed plan */
+} ffst_status;
+
+/* Which spectra to generate. */
+typedef enum {
+    FFST_SHEARLET_MEYER = 0,        /* psi1-hat of eq. (Psi1), cone scaling phi-hat
+                                       of eq. (phi); the paper's default */
+    FFST_SHEARLET_MEYER_SMOOTH = 1  /* smooth shearlets of Sec. 3.4: psi1-hat
+                                       replaced by eq. (newPsi1), tensor
+                                       low-pass Phi-hat of eq. (Phi) */
+} ffst_shearlet;
+
+typedef struct {
+    int max_scale_min;   /* 0: X = 2^(2J-1) ('max', the default); 1: X = 2^(2J-2)
+                            ('min'); option maxScale of Sec. 3.5.3 */
+    int shearlet;        /* an ffst_shearlet value */
+} ffst_options;
+
+/*
+ * Create a plan for M x N images with J scales (J <= 0 selects the default
+ * floor(1/2 log2 max(M, N)), Sec. 3.1) and generate its spectra on the
+ * current HIP device (Sec. 3.5.1 "we precompute these spectra"). The
+ * spectra are evaluated in float64 and stored in float32. Synchronous: on
+ * return the plan is ready. *out receives the plan, or NULL on failure.
+ */
+int ffst_spectra(int M, int N, int J, ffst_plan** out);
+
+/* Same with options (NULL = defaults). */
+int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** out);
+
+/* Sizes of a plan. Any output pointer may be NULL. */
+int ffst_plan_info(const ffst_plan* plan, int* M, int* N, int* J, int* eta);
+
+/* Bytes of workspace a transform call with this batch needs (0 on a bad plan
+ * or batch < 0). */
+size_t ffst_workspace_size(const ffst_plan* plan, int batch);
+
+/*
+ * Copy the plan's float32 spectra into device memory dst (stream-ordered on
+ * the default stream, then synchronised): full_plane = 0 writes
+ * [eta][M][N/2+1], full_plane = 1 writes [eta][M][N] (the missing columns by
+ * evenness, Psi(r, c) = Psi(-r mod M, -c mod N)).
+ */
+int ffst_get_spectra(const ffst_plan* plan, float* dst, int full_plane);
+
+/*
+ * Number of nonzero-column windows used to skip work: writes, for each
+ * spectrum i, the first and last column c in [0, N/2] where Psi_i has a
+ * nonzero value (host arrays of eta ints each; -1/-1 for an all-zero plane).
+ */
+int ffst_plan_windows(const ffst_plan* plan, int* first_col, int* last_col);
+
+/*
+ * Forward transform of `batch` images: coeffs[b][i] = ifft2(Psi_i .* fft2(f[b])).
+ * batch = 0 is a no-op. Asynchronous on `stream`.
+ */
+int ffst_forward(const ffst_plan* plan, const float* f, float* coeffs, int batch,
+                 void* ws, void* stream);
+
+/*
+ * Adjoint: f[b] = ifft2( sum_i Psi_i .* fft2(coeffs[b][i]) ). Overwrites f
+ * (does not accumulate). Asynchronous on `stream`.
+ */
+int ffst_adjoint(const ffst_plan* plan, const float* coeffs, float* f, int batch,
+                 void* ws, void* stream);
+
+/* Inverse transform; the same computation as ffst_adjoint (Parseval frame). */
+int ffst_inverse(const ffst_plan* plan, const float* coeffs, float* f, int batch,
+                 void* ws, void* stream);
+
+/* Release a plan (NULL is ignored). Synchronises the device first. */
+void ffst_destroy(ffst_plan* plan);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* ffst_last_error(void);
+
+/*
+ * Kernel timing. With profiling enabled, every launch of a kernel whose id
+ * bit is set in `mask` is bracketed by two HIP events recorded on the
+ * launch's own stream. ffst_profile_read synchronises on the recorded
+ * events and returns, for kernel `id`, the summed duration in milliseconds
+ * and the number of timed launches since the last reset. Kernel ids are
+ * 0 .. ffst_num_kernels()-1; ffst_kernel_name gives the HIP kernel's name.
+ * Not thread-safe; meant for benchmarks.
+ */
+int ffst_profile_enable(unsigned mask);
+int ffst_profile_read(int id, double* total_ms, long long* launches);
+int ffst_profile_reset(void);
+int ffst_num_kernels(void);
+const char* ffst_kernel_name(int id);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFST_H */

@@ -1,0 +1,162 @@
+"""ctypes binding of libffst.so: the C ABI declared in include/ffst.h, one
+Python function per C entry point, with the same names. Argument
+marshalling only; every step of the transform runs in the HIP kernels of
+the library. Fails loudly when the library is missing."""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffst.so")
+
+FFST_OK = 0
+FFST_EINVAL = 1
+FFST_EUNSUPPORTED = 2
+FFST_ENOMEM = 3
+FFST_EDEVICE = 4
+FFST_EBADPLAN = 5
+
+FFST_SHEARLET_MEYER = 0
+FFST_SHEARLET_MEYER_SMOOTH = 1
+
+EXPORTED = [
+    "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
+    "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
+    "ffst_inverse", "ffst_destroy", "ffst_last_error", "ffst_profile_enable",
+    "ffst_profile_read", "ffst_profile_reset", "ffst_num_kernels", "ffst_kernel_name",
+]
+
+
+class FfstError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where} failed with status {status}: {message}")
+        self.status = status
+
+
+class ffst_options(ctypes.Structure):
+    _fields_ = [("max_scale_min", ctypes.c_int), ("shearlet", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libffst.so (built in-tree by paper_1202_1773_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1202_1773_amd.build` (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    sig = {
+        "ffst_spectra": (I, [I, I, I, ctypes.POINTER(P)]),
+        "ffst_spectra_ex": (I, [I, I, I, ctypes.POINTER(ffst_options), ctypes.POINTER(P)]),
+        "ffst_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_workspace_size": (ctypes.c_size_t, [P, I]),
+        "ffst_get_spectra": (I, [P, P, I]),
+        "ffst_plan_windows": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_forward": (I, [P, P, P, I, P, P]),
+        "ffst_adjoint": (I, [P, P, P, I, P, P]),
+        "ffst_inverse": (I, [P, P, P, I, P, P]),
+        "ffst_destroy": (None, [P]),
+        "ffst_last_error": (ctypes.c_char_p, []),
+        "ffst_profile_enable": (I, [ctypes.c_uint]),
+        "ffst_profile_read": (I, [I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+        "ffst_profile_reset": (I, []),
+        "ffst_num_kernels": (I, []),
+        "ffst_kernel_name": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status != FFST_OK:
+        msg = load().ffst_last_error().decode()
+        raise FfstError(status, where, msg)
+
+
+# ---- thin wrappers with the C names ------------------------------------
+
+def ffst_spectra(M, N, J=0, max_scale="max", shearlet=FFST_SHEARLET_MEYER):
+    """Create a plan and generate its spectra; returns the opaque handle."""
+    lib = load()
+    out = ctypes.c_void_p()
+    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet))
+    _check(lib.ffst_spectra_ex(int(M), int(N), int(J), ctypes.byref(opt), ctypes.byref(out)), "ffst_spectra")
+    return out.value
+
+
+def ffst_plan_info(plan):
+    vals = [ctypes.c_int() for _ in range(4)]
+    _check(load().ffst_plan_info(plan, *[ctypes.byref(v) for v in vals]), "ffst_plan_info")
+    return tuple(v.value for v in vals)
+
+
+def ffst_workspace_size(plan, batch):
+    return int(load().ffst_workspace_size(plan, int(batch)))
+
+
+def ffst_get_spectra(plan, dst_ptr, full_plane=0):
+    _check(load().ffst_get_spectra(plan, ctypes.c_void_p(dst_ptr), int(full_plane)), "ffst_get_spectra")
+
+
+def ffst_plan_windows(plan, eta):
+    lo = (ctypes.c_int * eta)()
+    hi = (ctypes.c_int * eta)()
+    _check(load().ffst_plan_windows(plan, lo, hi), "ffst_plan_windows")
+    return list(lo), list(hi)
+
+
+def ffst_forward(plan, f_ptr, c_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_forward(plan, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), int(batch),
+                               ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_forward")
+
+
+def ffst_adjoint(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_adjoint(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
+                               ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_adjoint")
+
+
+def ffst_inverse(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_inverse(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
+                               ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_inverse")
+
+
+def ffst_destroy(plan):
+    if plan:
+        load().ffst_destroy(plan)
+
+
+def ffst_last_error():
+    return load().ffst_last_error().decode()
+
+
+def ffst_profile_enable(mask):
+    _check(load().ffst_profile_enable(ctypes.c_uint(mask)), "ffst_profile_enable")
+
+
+def ffst_profile_read(kernel_id):
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(load().ffst_profile_read(int(kernel_id), ctypes.byref(ms), ctypes.byref(n)), "ffst_profile_read")
+    return ms.value, n.value
+
+
+def ffst_profile_reset():
+    _check(load().ffst_profile_reset(), "ffst_profile_reset")
+
+
+def ffst_num_kernels():
+    return int(load().ffst_num_kernels())
+
+
+def ffst_kernel_name(kernel_id):
+    return load().ffst_kernel_name(int(kernel_id)).decode()

@@ -1,0 +1,449 @@
+// api.hip -- plan management and the C ABI declared in include/ffst.h.
+#include "../../include/ffst.h"
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ffst;
+
+struct ffst_plan {
+  int M = 0, N = 0, J = 0, eta = 0, H = 0;
+  int device = -1;
+  ffst_options opt{};
+  double delta = 0.0;
+  // device buffers owned by the plan
+  float* psi = nullptr;         // [eta][M][H]
+  float2* twM = nullptr;        // exp(-2 pi i m / M), m < M
+  float2* twN = nullptr;        // exp(-2 pi i m / N), m < N
+  int* d_lo = nullptr;          // per-plane window start, width, offset
+  int* d_w = nullptr;
+  long long* d_off = nullptr;
+  int* d_img_lo = nullptr;      // single full window for image-sized passes
+  int* d_img_w = nullptr;
+  long long* d_img_off = nullptr;
+  int2* d_items = nullptr;      // forward column tiles (spectrum, first column)
+  int* d_tile_ptr = nullptr;    // adjoint column tiles -> spectra (CSR)
+  int* d_tile_planes = nullptr;
+  // host copies
+  std::vector<int> lo, w;
+  std::vector<long long> off;
+  long long zimg = 0;           // complex elements of one image's compact buffer
+  int nitems = 0, ntiles = 0;
+  unsigned magic = 0;
+};
+
+namespace {
+
+constexpr unsigned kMagic = 0x46465354u;  // "FFST"
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int ok() { return FFST_OK; }
+
+bool plan_ok(const ffst_plan* p) { return p && p->magic == kMagic; }
+
+// ---- kernel timing -----------------------------------------------------
+const char* kKernelNames[KID_COUNT] = {
+    "k_spectra", "k_windows", "k_r2c_rows(image)", "k_fft_cols_image", "k_fwd_cols",
+    "k_c2r_rows(planes)", "k_r2c_rows(planes)", "k_adj_cols", "k_c2r_rows(image)", "k_expand"};
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+unsigned g_mask = 0;
+std::vector<ProfRec> g_recs;
+double g_total_ms[KID_COUNT] = {};
+long long g_count[KID_COUNT] = {};
+
+template <class Fn>
+hipError_t timed(int id, hipStream_t s, Fn&& fn) {
+  if (!((g_mask >> id) & 1u)) return fn();
+  ProfRec r{id, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return fn();
+  (void)hipEventRecord(r.a, s);
+  hipError_t e = fn();
+  (void)hipEventRecord(r.b, s);
+  g_recs.push_back(r);
+  return e;
+}
+
+void drain_profile() {
+  for (auto& r : g_recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_total_ms[r.id] += ms;
+      g_count[r.id] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_recs.clear();
+}
+
+// ---- plan construction -------------------------------------------------
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int default_scales(int M, int N) {
+  int L = std::max(M, N), lg = 0;
+  while ((L >> (lg + 1)) > 0) ++lg;  // floor(log2 L)
+  return lg / 2;
+}
+
+// Index order of Sec. 3.5.2: per scale h k = 0, -1 .. -2^j+1; seam -2^j;
+// v -2^j+1 .. 2^j-1; seam 2^j; h 2^j-1 .. 1. Low-pass first.
+void index_order(int J, std::vector<int>& kind, std::vector<int>& jj, std::vector<int>& kk) {
+  kind = {KIND_LOWPASS};
+  jj = {0};
+  kk = {0};
+  auto push = [&](int kd, int j, int k) {
+    kind.push_back(kd);
+    jj.push_back(j);
+    kk.push_back(k);
+  };
+  for (int j = 0; j < J; ++j) {
+    const int P = 1 << j;
+    for (int k = 0; k > -P; --k) push(KIND_H, j, k);
+    push(KIND_SEAM, j, -P);
+    for (int k = -P + 1; k < P; ++k) push(KIND_V, j, k);
+    push(KIND_SEAM, j, P);
+    for (int k = P - 1; k > 0; --k) push(KIND_H, j, k);
+  }
+}
+
+std::vector<float2> twiddles(int L) {
+  std::vector<float2> t(L);
+  for (int m = 0; m < L; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)L;
+    t[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return t;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_plan(ffst_plan* p) {
+  if (!p) return;
+  void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
+                  p->d_img_off, p->d_items, p->d_tile_ptr, p->d_tile_planes};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  p->magic = 0;
+  delete p;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t ws_bytes(const ffst_plan* p, int batch) {
+  const size_t fa = align256((size_t)batch * p->M * p->H * sizeof(float2));
+  const size_t yz = align256((size_t)batch * (size_t)p->zimg * sizeof(float2));
+  return fa + yz;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+int check_call(const ffst_plan* p, const void* in, size_t in_bytes, const void* out, size_t out_bytes,
+               int batch, const void* ws) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (batch < 0) return fail(FFST_EINVAL, "batch must be >= 0 (got %d)", batch);
+  if (batch == 0) return FFST_OK;
+  if (!in || !out) return fail(FFST_EINVAL, "input and output must be non-NULL");
+  if (!ws) return fail(FFST_EINVAL, "workspace must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(FFST_EINVAL, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8)
+    return fail(FFST_EINVAL, "input and output must be 8-byte aligned");
+  if (overlap(in, in_bytes, out, out_bytes)) return fail(FFST_EINVAL, "input and output overlap");
+  const size_t wsb = ws_bytes(p, batch);
+  if (overlap(ws, wsb, in, in_bytes) || overlap(ws, wsb, out, out_bytes))
+    return fail(FFST_EINVAL, "workspace overlaps input or output");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FFST_EDEVICE, "hipGetDevice failed");
+  if (dev != p->device)
+    return fail(FFST_EINVAL, "current device %d is not the plan's device %d", dev, p->device);
+  return FFST_OK;
+}
+
+int launched(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(FFST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return FFST_OK;
+}
+
+Windows plane_windows(const ffst_plan* p) { return Windows{p->d_lo, p->d_w, p->d_off}; }
+Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_w, p->d_img_off}; }
+
+}  // namespace
+
+extern "C" {
+
+int ffst_spectra(int M, int N, int J, ffst_plan** out) { return ffst_spectra_ex(M, N, J, nullptr, out); }
+
+int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** out) {
+  if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  if (M < 4 || N < 4) return fail(FFST_EINVAL, "image sides must be >= 4 (got %d x %d)", M, N);
+  ffst_options o{};
+  if (opt) o = *opt;
+  if (o.max_scale_min != 0 && o.max_scale_min != 1) return fail(FFST_EINVAL, "max_scale_min must be 0 or 1");
+  if (o.shearlet != FFST_SHEARLET_MEYER && o.shearlet != FFST_SHEARLET_MEYER_SMOOTH)
+    return fail(FFST_EINVAL, "unknown shearlet %d", o.shearlet);
+  if (J <= 0) J = default_scales(M, N);
+  if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
+  if (!is_pow2(M) || !is_pow2(N) || M < 8 || N < 8 || M > 4096 || N > 4096 || !supported_length(M))
+    return fail(FFST_EUNSUPPORTED, "GPU path supports powers of two in [8, 4096] (got %d x %d)", M, N);
+
+  ffst_plan* p = new (std::nothrow) ffst_plan();
+  if (!p) return fail(FFST_ENOMEM, "host allocation failed");
+  p->M = M;
+  p->N = N;
+  p->J = J;
+  p->H = N / 2 + 1;
+  p->eta = (1 << (J + 2)) - 3;
+  p->opt = o;
+  p->magic = kMagic;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free_plan(p);
+    return fail(FFST_EDEVICE, "hipGetDevice failed");
+  }
+  // Grid of Sec. 3.5.1: X = 2^(2J-1) ('max') or 2^(2J-2) ('min');
+  // Delta = 2X / (L_odd - 1) with L the larger side made odd.
+  const int L = std::max(M, N);
+  const int L_odd = (L % 2 == 0) ? L + 1 : L;
+  const double X = std::ldexp(1.0, 2 * J - 1 - o.max_scale_min);
+  p->delta = 2.0 * X / (double)(L_odd - 1);
+
+  std::vector<int> kind, jj, kk;
+  index_order(J, kind, jj, kk);
+  int *d_kind = nullptr, *d_j = nullptr, *d_k = nullptr;
+  int *d_lo = nullptr, *d_hi = nullptr;
+  const size_t psi_elems = (size_t)p->eta * M * p->H;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->psi), psi_elems * sizeof(float));
+  if (e != hipSuccess) {
+    free_plan(p);
+    return fail(FFST_ENOMEM, "spectra allocation (%zu bytes): %s", psi_elems * 4, hipGetErrorString(e));
+  }
+  std::vector<int> lo_init(p->eta, p->H), hi_init(p->eta, -1);
+  if ((e = upload(&p->twM, twiddles(M))) != hipSuccess || (e = upload(&p->twN, twiddles(N))) != hipSuccess ||
+      (e = upload(&d_kind, kind)) != hipSuccess || (e = upload(&d_j, jj)) != hipSuccess ||
+      (e = upload(&d_k, kk)) != hipSuccess || (e = upload(&d_lo, lo_init)) != hipSuccess ||
+      (e = upload(&d_hi, hi_init)) != hipSuccess) {
+    hipFree(d_kind); hipFree(d_j); hipFree(d_k); hipFree(d_lo); hipFree(d_hi);
+    free_plan(p);
+    return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
+  }
+  GenParams g{M, N, p->delta, o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? 1 : 0};
+  e = timed(KID_SPECTRA, nullptr, [&] { return launch_spectra(g, p->eta, d_kind, d_j, d_k, p->psi, nullptr); });
+  if (e == hipSuccess)
+    e = timed(KID_WINDOWS, nullptr, [&] { return launch_windows(p->psi, M, N, p->eta, d_lo, d_hi, nullptr); });
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<int> hi(p->eta);
+  p->lo.assign(p->eta, 0);
+  if (e == hipSuccess) e = hipMemcpy(p->lo.data(), d_lo, p->eta * sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hi.data(), d_hi, p->eta * sizeof(int), hipMemcpyDeviceToHost);
+  hipFree(d_kind); hipFree(d_j); hipFree(d_k); hipFree(d_lo); hipFree(d_hi);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return fail(FFST_EDEVICE, "spectra generation: %s", hipGetErrorString(e));
+  }
+
+  // Compact per-plane windows and the work lists of the column kernels.
+  const int TW = col_tile_width(M);
+  p->w.assign(p->eta, 0);
+  p->off.assign(p->eta, 0);
+  std::vector<int2> items;
+  long long acc = 0;
+  for (int i = 0; i < p->eta; ++i) {
+    if (hi[i] < p->lo[i]) {  // all-zero plane
+      p->lo[i] = 0;
+      p->w[i] = 0;
+    } else {
+      p->w[i] = hi[i] - p->lo[i] + 1;
+    }
+    p->off[i] = acc;
+    acc += (long long)M * p->w[i];
+    for (int c0 = p->lo[i]; c0 < p->lo[i] + p->w[i]; c0 += TW) items.push_back(make_int2(i, c0));
+  }
+  p->zimg = acc;
+  p->nitems = (int)items.size();
+  p->ntiles = (p->H + TW - 1) / TW;
+  std::vector<int> tile_ptr(p->ntiles + 1, 0), tile_planes;
+  for (int t = 0; t < p->ntiles; ++t) {
+    const int a = t * TW, b = a + TW;
+    for (int i = 0; i < p->eta; ++i)
+      if (p->w[i] > 0 && p->lo[i] < b && p->lo[i] + p->w[i] > a) tile_planes.push_back(i);
+    tile_ptr[t + 1] = (int)tile_planes.size();
+  }
+  std::vector<int> img_lo{0}, img_w{p->H};
+  std::vector<long long> img_off{0};
+  if ((e = upload(&p->d_lo, p->lo)) != hipSuccess || (e = upload(&p->d_w, p->w)) != hipSuccess ||
+      (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
+      (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
+      (e = upload(&p->d_items, items)) != hipSuccess || (e = upload(&p->d_tile_ptr, tile_ptr)) != hipSuccess ||
+      (e = upload(&p->d_tile_planes, tile_planes)) != hipSuccess) {
+    free_plan(p);
+    return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return ok();
+}
+
+int ffst_plan_info(const ffst_plan* p, int* M, int* N, int* J, int* eta) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (M) *M = p->M;
+  if (N) *N = p->N;
+  if (J) *J = p->J;
+  if (eta) *eta = p->eta;
+  return ok();
+}
+
+size_t ffst_workspace_size(const ffst_plan* p, int batch) {
+  if (!plan_ok(p) || batch < 0) return 0;
+  return ws_bytes(p, batch);
+}
+
+int ffst_get_spectra(const ffst_plan* p, float* dst, int full_plane) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (!dst) return fail(FFST_EINVAL, "dst must be non-NULL");
+  if (full_plane != 0 && full_plane != 1) return fail(FFST_EINVAL, "full_plane must be 0 or 1");
+  hipError_t e;
+  if (!full_plane) {
+    e = hipMemcpy(dst, p->psi, (size_t)p->eta * p->M * p->H * sizeof(float), hipMemcpyDeviceToDevice);
+  } else {
+    e = timed(KID_EXPAND, nullptr, [&] { return launch_expand(p->psi, p->M, p->N, p->eta, dst, nullptr); });
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  return launched(e, "ffst_get_spectra");
+}
+
+int ffst_plan_windows(const ffst_plan* p, int* first_col, int* last_col) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (!first_col || !last_col) return fail(FFST_EINVAL, "outputs must be non-NULL");
+  for (int i = 0; i < p->eta; ++i) {
+    first_col[i] = p->w[i] ? p->lo[i] : -1;
+    last_col[i] = p->w[i] ? p->lo[i] + p->w[i] - 1 : -1;
+  }
+  return ok();
+}
+
+int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  const size_t img = (size_t)p->M * p->N * sizeof(float);
+  int st = check_call(p, f, img * (size_t)std::max(batch, 0), coeffs, img * p->eta * (size_t)std::max(batch, 0),
+                      batch, ws);
+  if (st != FFST_OK || batch == 0) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* F = static_cast<float2*>(ws);
+  float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) +
+                                        align256((size_t)batch * p->M * p->H * sizeof(float2)));
+  const long long M = p->M;
+  const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
+  hipError_t e = timed(KID_R2C_IMAGE, s, [&] {
+    return launch_r2c_rows(p->N, f, batch * M, p->M, 1, F, M * p->H, image_window(p), p->twN, s);
+  });
+  if (e == hipSuccess)
+    e = timed(KID_FFT_COLS_IMAGE, s, [&] { return launch_fft_cols_image(p->M, p->N, F, batch, p->twM, s); });
+  if (e == hipSuccess && p->nitems > 0)
+    e = timed(KID_FWD_COLS, s, [&] {
+      return launch_fwd_cols(p->M, p->N, F, p->psi, batch, p->d_items, p->nitems, plane_windows(p), p->zimg, Y,
+                             scale, p->twM, s);
+    });
+  if (e == hipSuccess)
+    e = timed(KID_C2R_PLANES, s, [&] {
+      return launch_c2r_rows(p->N, Y, p->zimg, plane_windows(p), (long long)batch * p->eta * M, p->M, p->eta,
+                             coeffs, 1.0f, p->twN, s);
+    });
+  return launched(e, "ffst_forward");
+}
+
+int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  const size_t img = (size_t)p->M * p->N * sizeof(float);
+  int st = check_call(p, coeffs, img * p->eta * (size_t)std::max(batch, 0), f, img * (size_t)std::max(batch, 0),
+                      batch, ws);
+  if (st != FFST_OK || batch == 0) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* A = static_cast<float2*>(ws);
+  float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) +
+                                        align256((size_t)batch * p->M * p->H * sizeof(float2)));
+  const long long M = p->M;
+  const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
+  hipError_t e = timed(KID_R2C_PLANES, s, [&] {
+    return launch_r2c_rows(p->N, coeffs, (long long)batch * p->eta * M, p->M, p->eta, Z, p->zimg,
+                           plane_windows(p), p->twN, s);
+  });
+  if (e == hipSuccess)
+    e = timed(KID_ADJ_COLS, s, [&] {
+      return launch_adj_cols(p->M, p->N, Z, p->zimg, plane_windows(p), p->psi, batch, p->d_tile_ptr,
+                             p->d_tile_planes, p->ntiles, A, scale, p->twM, s);
+    });
+  if (e == hipSuccess)
+    e = timed(KID_C2R_IMAGE, s, [&] {
+      return launch_c2r_rows(p->N, A, M * p->H, image_window(p), batch * M, p->M, 1, f, 1.0f, p->twN, s);
+    });
+  return launched(e, "ffst_adjoint");
+}
+
+int ffst_inverse(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  return ffst_adjoint(p, coeffs, f, batch, ws, stream);
+}
+
+void ffst_destroy(ffst_plan* p) {
+  if (!plan_ok(p)) return;
+  hipDeviceSynchronize();
+  free_plan(p);
+}
+
+const char* ffst_last_error(void) { return g_err.c_str(); }
+
+int ffst_profile_enable(unsigned mask) {
+  g_mask = mask;
+  return FFST_OK;
+}
+
+int ffst_profile_read(int id, double* total_ms, long long* launches) {
+  if (id < 0 || id >= KID_COUNT) return fail(FFST_EINVAL, "kernel id %d out of range", id);
+  drain_profile();
+  if (total_ms) *total_ms = g_total_ms[id];
+  if (launches) *launches = g_count[id];
+  return FFST_OK;
+}
+
+int ffst_profile_reset(void) {
+  drain_profile();
+  std::fill(g_total_ms, g_total_ms + KID_COUNT, 0.0);
+  std::fill(g_count, g_count + KID_COUNT, 0LL);
+  return FFST_OK;
+}
+
+int ffst_num_kernels(void) { return KID_COUNT; }
+
+const char* ffst_kernel_name(int id) { return (id >= 0 && id < KID_COUNT) ? kKernelNames[id] : ""; }
+
+}  // extern "C"

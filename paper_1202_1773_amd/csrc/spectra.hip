@@ -1,0 +1,169 @@
+// spectra.hip -- shearlet spectra on the frequency grid, evaluated in float64
+// on the device and stored in float32 (run once per plan).
+//
+// Grid (Sec. 3.5.1): omega_1 = Delta * q_N(c) along columns, omega_2 =
+// Delta * q_M(r) along rows, q_D(p) = p for p <= ceil(D/2) - 1 and p - D
+// otherwise (natural DFT order). Only the half plane c = 0 .. N/2 is stored.
+//
+// Windows (Sec. 2.1, 2.4, 3.4):
+//   v(x)      = x^4 (35 - 84 x + 70 x^2 - 20 x^3) on [0, 1], clamped outside
+//   psi1(w)   = 0 | sin(pi/2 v(2|w|-1)) | 1 | cos(pi/2 v(|w|/2-1)) | 0 on the
+//               breakpoints 1/2, 1, 2, 4 (the closed form of Sec. 3.4)
+//   psi2(w)   = sqrt(v(1 - |w|))
+//   varphi(w) = 1 | cos(pi/2 v(2|w|-1)) | 0 on the breakpoints 1/2, 1
+// Spectra (Sec. 3.1, eq. shearletTransform):
+//   low-pass  varphi(max(|w1|, |w2|))                           (eq. phi)
+//   (h, j, k) psi1(4^-j w1) psi2(2^j w2/w1 + k)  where |w2| < |w1|
+//   (v, j, k) psi1(4^-j w2) psi2(2^j w1/w2 + k)  where |w1| < |w2|
+//   seam      h formula where |w2| <= |w1| (w1 != 0), v formula elsewhere
+// Smooth variant (Sec. 3.4, eq. newPsi1, eq. smoothPsi): psi1(4^-j w_a) is
+// replaced by sqrt(Phi^2(w/4^(j+1)) - Phi^2(w/4^j)) with the tensor low-pass
+// Phi(w) = varphi(w1) varphi(w2) (eq. Phi), which is also the low-pass.
+// Real coefficients (Sec. 3.8.1): on the Nyquist column (N even) the value at
+// row r and the value at row -r mod M are both replaced by their root mean
+// square; on the Nyquist row (M even) likewise for columns c and -c mod N.
+#include "internal.hpp"
+
+#include <math.h>
+
+namespace ffst {
+namespace {
+
+__device__ double v_aux(double x) {
+  if (x <= 0.0) return 0.0;
+  if (x >= 1.0) return 1.0;
+  const double x2 = x * x;
+  return x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+}
+
+__device__ double psi1_hat(double w) {
+  const double a = fabs(w);
+  if (a <= 0.5) return 0.0;
+  if (a < 1.0) return sin(M_PI_2 * v_aux(2.0 * a - 1.0));
+  if (a <= 2.0) return 1.0;
+  if (a < 4.0) return cos(M_PI_2 * v_aux(0.5 * a - 1.0));
+  return 0.0;
+}
+
+__device__ double psi2_hat(double w) { return sqrt(v_aux(1.0 - fabs(w))); }
+
+__device__ double varphi(double w) {
+  const double a = fabs(w);
+  if (a <= 0.5) return 1.0;
+  if (a < 1.0) return cos(M_PI_2 * v_aux(2.0 * a - 1.0));
+  return 0.0;
+}
+
+// Smooth corona function of Sec. 3.4 at the dilated point 4^-j w.
+__device__ double corona(double w1, double w2, double dil) {
+  const double a1 = w1 * dil, a2 = w2 * dil;
+  const double outer = varphi(0.25 * a1) * varphi(0.25 * a2);
+  const double inner = varphi(a1) * varphi(a2);
+  const double d = outer * outer - inner * inner;
+  return d > 0.0 ? sqrt(d) : 0.0;
+}
+
+__device__ double spectrum_value(int kind, int j, int k, int smooth, double w1, double w2) {
+  const double a1 = fabs(w1), a2 = fabs(w2);
+  if (kind == KIND_LOWPASS) {
+    if (smooth) return varphi(w1) * varphi(w2);
+    return a2 <= a1 ? varphi(w1) : varphi(w2);
+  }
+  const double dil = ldexp(1.0, -2 * j);   // 4^-j
+  const double shr = ldexp(1.0, j);        // 2^j
+  const bool use_v = (kind == KIND_V) ? (a1 < a2) : (kind == KIND_SEAM && a1 < a2);
+  const bool use_h = (kind == KIND_H) ? (a2 < a1) : (kind == KIND_SEAM && !(a1 < a2) && a1 > 0.0);
+  if (use_h) {
+    const double radial = smooth ? corona(w1, w2, dil) : psi1_hat(w1 * dil);
+    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w2 / w1) + k);
+  }
+  if (use_v) {
+    const double radial = smooth ? corona(w1, w2, dil) : psi1_hat(w2 * dil);
+    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w1 / w2) + k);
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ int signed_freq(int p, int D) { return p <= (D + 1) / 2 - 1 ? p : p - D; }
+
+__device__ double grid_value(const GenParams& g, int kind, int j, int k, int r, int c) {
+  const double w1 = g.delta * signed_freq(c, g.N);
+  const double w2 = g.delta * signed_freq(r, g.M);
+  return spectrum_value(kind, j, k, g.smooth, w1, w2);
+}
+
+__global__ void __launch_bounds__(256) k_spectra(GenParams g, const int* __restrict__ kind,
+                                                 const int* __restrict__ jj, const int* __restrict__ kk,
+                                                 float* __restrict__ psi) {
+  const int H = g.N / 2 + 1;
+  const long long n = (long long)g.M * H;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (idx >= n) return;
+  const int r = (int)(idx / H), c = (int)(idx % H);
+  const int kd = kind[i], j = jj[i], k = kk[i];
+  double val = grid_value(g, kd, j, k, r, c);
+  if (g.N % 2 == 0 && c == g.N / 2) {
+    const double b = grid_value(g, kd, j, k, (g.M - r) % g.M, c);
+    val = sqrt(0.5 * (val * val + b * b));
+  } else if (g.M % 2 == 0 && r == g.M / 2) {
+    const double b = grid_value(g, kd, j, k, r, (g.N - c) % g.N);
+    val = sqrt(0.5 * (val * val + b * b));
+  }
+  psi[(long long)i * n + idx] = (float)val;
+}
+
+// First and last half-plane column holding a nonzero value, per plane.
+__global__ void __launch_bounds__(256) k_windows(const float* __restrict__ psi, int M, int H,
+                                                 int* __restrict__ lo, int* __restrict__ hi) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (c >= H) return;
+  const float* p = psi + (long long)i * M * H + c;
+  bool any = false;
+  for (int r = 0; r < M && !any; ++r) any = p[(long long)r * H] != 0.0f;
+  if (any) {
+    atomicMin(lo + i, c);
+    atomicMax(hi + i, c);
+  }
+}
+
+// Full-plane copy: columns beyond N/2 by evenness on the grid.
+__global__ void __launch_bounds__(256) k_expand(const float* __restrict__ psi, int M, int N,
+                                                float* __restrict__ out) {
+  const int H = N / 2 + 1;
+  const long long n = (long long)M * N;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (idx >= n) return;
+  const int r = (int)(idx / N), c = (int)(idx % N);
+  const int rr = c < H ? r : (M - r) % M;
+  const int cc = c < H ? c : N - c;
+  out[(long long)i * n + idx] = psi[(long long)i * M * H + (long long)rr * H + cc];
+}
+
+}  // namespace
+
+hipError_t launch_spectra(const GenParams& g, int eta, const int* kind, const int* jj, const int* kk,
+                          float* psi, hipStream_t s) {
+  const long long n = (long long)g.M * (g.N / 2 + 1);
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)eta);
+  hipLaunchKernelGGL(k_spectra, grid, dim3(256), 0, s, g, kind, jj, kk, psi);
+  return hipGetLastError();
+}
+
+hipError_t launch_windows(const float* psi, int M, int N, int eta, int* lo, int* hi, hipStream_t s) {
+  const int H = N / 2 + 1;
+  dim3 grid((unsigned)((H + 255) / 256), (unsigned)eta);
+  hipLaunchKernelGGL(k_windows, grid, dim3(256), 0, s, psi, M, H, lo, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const float* psi, int M, int N, int eta, float* out, hipStream_t s) {
+  const long long n = (long long)M * N;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)eta);
+  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, s, psi, M, N, out);
+  return hipGetLastError();
+}
+
+}  // namespace ffst

@@ -1,0 +1,111 @@
+"""Torch-facing plan object over the C ABI (device memory and streams only)."""
+
+import torch
+
+from . import _lib
+
+_SHEARLETS = {"meyer": _lib.FFST_SHEARLET_MEYER, "smooth": _lib.FFST_SHEARLET_MEYER_SMOOTH}
+
+
+class Plan:
+    """Spectra and tables for M x N images with J scales on one GPU.
+
+    forward(x):  x (M, N) or (B, M, N) float32 -> (eta, M, N) or (B, eta, M, N)
+    adjoint(c):  the reverse shapes; inverse(c) is the same computation.
+    Calls are asynchronous on torch's current stream of the plan's device.
+    One workspace per batch size is cached on the plan, so calls that may
+    run at the same time on different streams need their own `ws`.
+    """
+
+    def __init__(self, M, N, J=0, max_scale="max", shearlet="meyer", device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1202_1773_amd needs a ROCm GPU (no CPU path exists)")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._h = None
+        with torch.cuda.device(self.device):
+            self._h = _lib.ffst_spectra(M, N, J, max_scale, _SHEARLETS[shearlet])
+        self.M, self.N, self.J, self.eta = _lib.ffst_plan_info(self._h)
+        self.max_scale = max_scale
+        self.shearlet = shearlet
+        self._ws = {}
+
+    # ---------------------------------------------------------------- memory
+    def workspace_size(self, batch):
+        return _lib.ffst_workspace_size(self._h, batch)
+
+    def workspace(self, batch):
+        ws = self._ws.get(batch)
+        if ws is None:
+            nbytes = max(self.workspace_size(batch), 1)
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws[batch] = ws
+        ptr = ws.data_ptr()
+        return ptr + (-ptr) % 256
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, t, trailing):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float32:
+            raise ValueError(f"expected a float32 tensor on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor")
+        if tuple(t.shape[-len(trailing):]) != trailing:
+            raise ValueError(f"expected trailing shape {trailing}, got {tuple(t.shape)}")
+
+    # ------------------------------------------------------------ transforms
+    def forward(self, x, out=None, ws=None):
+        self._check(x, (self.M, self.N))
+        single = x.dim() == 2
+        xb = x.reshape(-1, self.M, self.N)
+        B = xb.shape[0]
+        if out is None:
+            out = torch.empty((B, self.eta, self.M, self.N), dtype=torch.float32, device=self.device)
+        self._check(out, (self.eta, self.M, self.N))
+        if out.numel() != B * self.eta * self.M * self.N:
+            raise ValueError("output has the wrong number of elements")
+        _lib.ffst_forward(self._h, xb.data_ptr(), out.data_ptr(), B,
+                          ws if ws is not None else self.workspace(B), self._stream())
+        return out.reshape(self.eta, self.M, self.N) if single else out.reshape(B, self.eta, self.M, self.N)
+
+    def adjoint(self, c, out=None, ws=None):
+        self._check(c, (self.eta, self.M, self.N))
+        single = c.dim() == 3
+        cb = c.reshape(-1, self.eta, self.M, self.N)
+        B = cb.shape[0]
+        if out is None:
+            out = torch.empty((B, self.M, self.N), dtype=torch.float32, device=self.device)
+        self._check(out, (self.M, self.N))
+        if out.numel() != B * self.M * self.N:
+            raise ValueError("output has the wrong number of elements")
+        _lib.ffst_adjoint(self._h, cb.data_ptr(), out.data_ptr(), B,
+                          ws if ws is not None else self.workspace(B), self._stream())
+        return out.reshape(self.M, self.N) if single else out.reshape(B, self.M, self.N)
+
+    def inverse(self, c, out=None, ws=None):
+        return self.adjoint(c, out=out, ws=ws)
+
+    # --------------------------------------------------------------- helpers
+    def spectra(self, full_plane=False):
+        """The plan's float32 spectra, (eta, M, N/2+1) or (eta, M, N)."""
+        cols = self.N if full_plane else self.N // 2 + 1
+        dst = torch.empty((self.eta, self.M, cols), dtype=torch.float32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _lib.ffst_get_spectra(self._h, dst.data_ptr(), 1 if full_plane else 0)
+        return dst
+
+    def windows(self):
+        """Per spectrum, the first and last half-plane column holding a nonzero."""
+        return _lib.ffst_plan_windows(self._h, self.eta)
+
+    def close(self):
+        if self._h:
+            _lib.ffst_destroy(self._h)
+            self._h = None
+        self._ws.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

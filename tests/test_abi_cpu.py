@@ -1,0 +1,83 @@
+"""The C ABI on the CPU: the library loads, exports every function declared
+in include/ffst.h, and rejects bad arguments before any device call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1202_1773_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ffst.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffst_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libffst.so is not built (run python -m paper_1202_1773_amd.build)")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(_lib.EXPORTED)
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_spectra_rejects_bad_arguments(lib):
+    out = ctypes.c_void_p(1)
+    assert lib.ffst_spectra(0, 64, 2, ctypes.byref(out)) == _lib.FFST_EINVAL
+    assert out.value is None
+    assert "sides" in _lib.ffst_last_error()
+    assert lib.ffst_spectra(64, 64, 11, ctypes.byref(out)) == _lib.FFST_EINVAL
+    assert lib.ffst_spectra(64, 64, 2, None) == _lib.FFST_EINVAL
+    # valid transform sizes that this GPU path does not run
+    assert lib.ffst_spectra(384, 512, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(63, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(8192, 8192, 0, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    bad = _lib.ffst_options(2, 0)
+    assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
+    bad = _lib.ffst_options(0, 7)
+    assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
+
+
+def test_calls_reject_bad_plans(lib):
+    z = ctypes.c_int()
+    assert lib.ffst_plan_info(None, ctypes.byref(z), None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_workspace_size(None, 1) == 0
+    assert lib.ffst_forward(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_adjoint(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_inverse(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_get_spectra(None, None, 0) == _lib.FFST_EBADPLAN
+    assert lib.ffst_plan_windows(None, None, None) == _lib.FFST_EBADPLAN
+    assert "plan" in _lib.ffst_last_error()
+    lib.ffst_destroy(None)  # ignored
+
+
+def test_profiling_table(lib):
+    n = lib.ffst_num_kernels()
+    assert n >= 9
+    names = [_lib.ffst_kernel_name(i) for i in range(n)]
+    assert "k_fwd_cols" in names and "k_adj_cols" in names
+    assert lib.ffst_kernel_name(n) == b""
+    with pytest.raises(_lib.FfstError):
+        _lib.ffst_profile_read(n)
+
+
+def test_python_wrappers_raise(lib):
+    with pytest.raises(_lib.FfstError) as e:
+        _lib.ffst_spectra(384, 512, 3)
+    assert e.value.status == _lib.FFST_EUNSUPPORTED

@@ -1,0 +1,193 @@
+"""HIP path against the FP64 oracle, through the C ABI (GPU only).
+
+Bar (from the benchmark spec of the method's accuracy target): relative L2
+error <= 1e-5 on every coefficient plane and for the adjoint/reconstruction;
+spectra within one float32 rounding (1.2e-7) of the oracle's float64 values.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_1773_amd import Plan, _lib
+from paper_1202_1773_amd.synthetic import cartoon, config1_image, config2_batch, gaussian
+
+from gpu_helpers import (log, oracle_adjoint, oracle_forward, oracle_spectra, per_plane_rel_l2,
+                         rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+SPECTRA_CASES = [(8, 8, 1), (64, 64, 2), (16, 16, 2), (512, 512, 3), (256, 512, 3),
+                 (512, 256, 3), (128, 64, 3), (1024, 1024, 5)]
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("M,N,J", SPECTRA_CASES)
+def test_spectra_match_oracle(M, N, J):
+    log(f"spectra {M}x{N} J={J}")
+    plan = Plan(M, N, J)
+    got = plan.spectra(full_plane=False).cpu().numpy().astype(np.float64)
+    ref = oracle_spectra(M, N, J)[:, :, : N // 2 + 1]
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1.2e-7
+    full = plan.spectra(full_plane=True).cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(full - oracle_spectra(M, N, J))) <= 1.2e-7
+    # float32 frame identity on the device copy
+    assert np.max(np.abs((full ** 2).sum(0) - 1.0)) < 1e-6
+    # skipped columns really hold only zeros
+    lo, hi = plan.windows()
+    for i in range(plan.eta):
+        nz = np.nonzero(np.any(got[i] != 0.0, axis=0))[0]
+        assert lo[i] == nz.min() and hi[i] == nz.max()
+    plan.close()
+
+
+def _forward_case(M, N, J, imgs):
+    plan = Plan(M, N, J)
+    x = torch.from_numpy(imgs).to(_dev())
+    c = plan.forward(x).cpu().numpy()
+    for b in range(imgs.shape[0]):
+        ref = oracle_forward(imgs[b], M, N, J)
+        err = per_plane_rel_l2(c[b], ref)
+        log(f"  fwd {M}x{N} J={J} b={b} max plane relL2 {err.max():.2e}")
+        assert err.max() <= TOL, (b, int(err.argmax()), err.max())
+    return plan, x, c
+
+
+FWD_CASES = [(64, 64, 2, "config1"), (512, 512, 3, "config2"), (256, 512, 3, "cartoon"),
+             (512, 256, 3, "cartoon"), (8, 8, 1, "gauss"), (16, 16, 2, "gauss"), (128, 64, 3, "cartoon"),
+             (64, 128, 2, "gauss")]
+
+
+def _images(kind, M, N, B=1):
+    if kind == "config1":
+        return config1_image()[None]
+    if kind == "config2":
+        return config2_batch(B)
+    if kind == "gauss":
+        return np.stack([gaussian(M, N, seed=102 + b) for b in range(B)])
+    return np.stack([cartoon(M, N, 12, 4, 0.1, seed=7 + b) for b in range(B)])
+
+
+@pytest.mark.parametrize("M,N,J,kind", FWD_CASES)
+def test_forward_adjoint_match_oracle(M, N, J, kind):
+    log(f"forward/adjoint {M}x{N} J={J} {kind}")
+    imgs = _images(kind, M, N)
+    plan, x, c = _forward_case(M, N, J, imgs)
+    # adjoint of the same float32 coefficients on both sides
+    ct = torch.from_numpy(c).to(_dev())
+    y = plan.adjoint(ct).cpu().numpy()
+    yref = oracle_adjoint(c[0], M, N, J)
+    e_adj = rel_l2(y[0], yref)
+    e_rec = rel_l2(y[0], imgs[0])
+    log(f"  adjoint relL2 {e_adj:.2e} reconstruction relL2 {e_rec:.2e}")
+    assert e_adj <= TOL and e_rec <= TOL
+    # inverse is the same computation
+    z = plan.inverse(ct).cpu().numpy()
+    assert np.array_equal(z, y)
+    # energy (Parseval frame)
+    e = abs(np.sum(c.astype(np.float64) ** 2) / np.sum(imgs.astype(np.float64) ** 2) - 1)
+    assert e <= TOL
+    plan.close()
+
+
+def test_batched_equals_separate_and_is_deterministic():
+    log("batch B=4 512x512 J=3 against single-image calls")
+    imgs = config2_batch(4)
+    plan = Plan(512, 512, 3)
+    x = torch.from_numpy(imgs).to(_dev())
+    c4 = plan.forward(x)
+    c4b = plan.forward(x)
+    assert torch.equal(c4, c4b)
+    for b in range(4):
+        assert torch.equal(plan.forward(x[b]), c4[b])
+    y4 = plan.adjoint(c4)
+    assert torch.equal(plan.adjoint(c4), y4)
+    for b in range(4):
+        assert torch.equal(plan.adjoint(c4[b]), y4[b])
+    plan.close()
+
+
+def test_bench_configuration_sampled():
+    # The benchmark runs 16 images of 512x512, J = 3, in one call per
+    # direction; check sampled images against the oracle in that launch shape.
+    log("bench launch shape 16x512x512 J=3, sampled parity")
+    imgs = config2_batch(16)
+    plan = Plan(512, 512, 3)
+    x = torch.from_numpy(imgs).to(_dev())
+    c = plan.forward(x)
+    y = plan.adjoint(c)
+    torch.cuda.synchronize()
+    cn, yn = c.cpu().numpy(), y.cpu().numpy()
+    for b in (0, 9, 15):
+        err = per_plane_rel_l2(cn[b], oracle_forward(imgs[b], 512, 512, 3))
+        assert err.max() <= TOL
+        assert rel_l2(yn[b], imgs[b]) <= TOL
+    plan.close()
+
+
+def test_large_2048_sampled_planes_and_properties():
+    # 2048 x 2048, J = 5 (125 spectra, ~2.1 GB of coefficients): sampled
+    # planes against the oracle (streamed one plane at a time), then
+    # reconstruction, energy and the adjoint dot-product identity, which hold
+    # at any size.
+    from paper_1202_1773_amd.synthetic import config5_image
+    log("2048x2048 J=5")
+    f = config5_image()
+    plan = Plan(2048, 2048, 5)
+    assert plan.eta == 125
+    x = torch.from_numpy(f).to(_dev())
+    c = plan.forward(x)
+    planes = [0, 1, 62, 64, 124]
+    ref = oracle_forward(f, 2048, 2048, 5, planes=planes)
+    got = c[planes].cpu().numpy()
+    err = per_plane_rel_l2(got, ref)
+    log(f"  sampled planes relL2 {err}")
+    assert err.max() <= TOL
+    y = plan.adjoint(c)
+    assert rel_l2(y.cpu().numpy(), f) <= TOL
+    cd = c.double()
+    assert abs((cd * cd).sum().item() / float((x.double() ** 2).sum()) - 1) <= TOL
+    g = torch.Generator(device="cuda").manual_seed(3)
+    r = torch.randn(c.shape, device=_dev(), generator=g)
+    lhs = (cd * r.double()).sum().item()
+    rhs = (x.double() * plan.adjoint(r).double()).sum().item()
+    assert abs(lhs - rhs) <= TOL * float(torch.linalg.norm(cd) * torch.linalg.norm(r.double()))
+    del c, cd, r
+    plan.close()
+
+
+def test_constant_and_zero_batch():
+    plan = Plan(64, 64, 2)
+    x = torch.full((64, 64), 2.5, device=_dev())
+    c = plan.forward(x)
+    assert torch.allclose(c[0], torch.full_like(c[0], 2.5), atol=1e-6)
+    assert c[1:].abs().max().item() < 1e-6
+    # batch 0: a no-op through the ABI
+    _lib.ffst_forward(plan._h, x.data_ptr(), c.data_ptr(), 0, 0, 0)
+    _lib.ffst_adjoint(plan._h, c.data_ptr(), x.data_ptr(), 0, 0, 0)
+    plan.close()
+
+
+def test_abi_errors_on_device():
+    plan = Plan(64, 64, 2)
+    x = torch.zeros((64, 64), device=_dev())
+    c = torch.zeros((13, 64, 64), device=_dev())
+    with pytest.raises(_lib.FfstError) as e:
+        _lib.ffst_forward(plan._h, x.data_ptr(), c.data_ptr(), 1, 0, 0)   # no workspace
+    assert e.value.status == _lib.FFST_EINVAL
+    ws = plan.workspace(1)
+    with pytest.raises(_lib.FfstError):
+        _lib.ffst_forward(plan._h, x.data_ptr(), x.data_ptr(), 1, ws, 0)  # aliasing
+    with pytest.raises(_lib.FfstError):
+        _lib.ffst_forward(plan._h, x.data_ptr(), c.data_ptr(), -1, ws, 0)
+    with pytest.raises(_lib.FfstError):
+        _lib.ffst_forward(plan._h, x.data_ptr(), c.data_ptr(), 1, ws + 8, 0)  # misaligned ws
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((32, 64), device=_dev()))
+    plan.close()
