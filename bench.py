@@ -1,0 +1,266 @@
+"""Benchmark: FFST forward + adjoint, 512 x 512 images, J = 3 (29 spectra), float32.
+
+One step = forward transform and adjoint transform of one batch of B
+synthetic cartoon images (default B = 16) in one call per direction (the
+batched form). The plain form (one image per call) is timed on the same
+images and reported alongside.
+
+Prints ONE JSON line:
+  value        Gcoef/s of the batched form = B * eta * M * N * steps / time
+  roofline     the dominant kernel's algorithmic bytes per launch over its
+               average duration (HIP events on the launch stream, timed
+               region), against MI355X HBM peak 8 TB/s; `traffic` comes from
+               the committed rocprofv3 counter summary when it was taken on
+               the current kernel sources, else null
+  path_roofline  the whole step's algorithmic bytes over the step time
+  cpu_baseline the FP64 CPU oracle on a bounded sample (1 thread)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gcoef/s fwd+adjoint @512² J=3 FP32 (%HBM roofline); batched vs plain"
+KERNEL_SOURCES = ["fft_core.hpp", "transform.hip", "spectra.hip", "internal.hpp", "api.hip"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1202_1773_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, M, N, J, B):
+    """HBM bytes per launch of `kernel` from profiles/traffic_*.md, if that
+    summary was measured on the current kernel sources and this workload."""
+    path = os.path.join(ROOT, "profiles", "traffic_ffst_512x512_J3_B16.md")
+    if not os.path.exists(path):
+        return None
+    want = source_hash()
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+            if (rec.get("kernel") == kernel and rec.get("source_sha") == want
+                    and rec.get("workload") == [M, N, J, B]):
+                return rec["bytes_per_launch"]
+    return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(M, N, J, images):
+    """The FP64 oracle, as it stands, on a bounded sample: forward + adjoint
+    of the given images on one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import spectra as ospec
+    from oracle import transform as otr
+
+    with threadpool_limits(1):
+        psi = ospec.spectra(M, N, J)          # plan creation, not timed (as on the GPU)
+        t0 = time.perf_counter()
+        for f in images:
+            c = otr.forward(f.astype(np.float64), psi)
+            otr.adjoint(c, psi)
+        dt = time.perf_counter() - t0
+    coef = len(images) * psi.shape[0] * M * N
+    return {"value": coef / dt / 1e9, "unit": "Gcoef/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(images)} image(s) of {M}x{N}, J={J}: forward+adjoint, FP64 NumPy, "
+                      f"{dt:.1f} s on {cpu_model()} (os.cpu_count()={os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--scales", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-images", type=int, default=3)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1202_1773_amd import Plan, _lib
+    from paper_1202_1773_amd.synthetic import config2_batch
+
+    M = N = args.size
+    J = args.scales
+    B = args.batch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    plan = Plan(M, N, J)
+    eta = plan.eta
+    imgs = config2_batch(B) if M == 512 else np.stack(
+        [__import__("paper_1202_1773_amd.synthetic", fromlist=["cartoon"]).cartoon(M, N, 20, 10, 0.1, 201 + b)
+         for b in range(B)])
+    x = torch.from_numpy(imgs).to(dev)
+    c = torch.empty((B, eta, M, N), dtype=torch.float32, device=dev)
+    y = torch.empty((B, M, N), dtype=torch.float32, device=dev)
+    c1 = torch.empty((eta, M, N), dtype=torch.float32, device=dev)
+    y1 = torch.empty((M, N), dtype=torch.float32, device=dev)
+    plan.workspace(B)
+    plan.workspace(1)
+
+    def step_batched():
+        plan.forward(x, out=c)
+        plan.adjoint(c, out=y)
+
+    def step_plain():
+        for b in range(B):
+            plan.forward(x[b], out=c1)
+            plan.adjoint(c1, out=y1)
+
+    # warm-up, with every kernel timed to find the dominant one
+    _lib.ffst_profile_reset()
+    _lib.ffst_profile_enable(0xFFFFFFFF)
+    for _ in range(args.warmup):
+        step_batched()
+    torch.cuda.synchronize()
+    nk = _lib.ffst_num_kernels()
+    per_kernel = {}
+    for k in range(nk):
+        ms, n = _lib.ffst_profile_read(k)
+        if n:
+            per_kernel[_lib.ffst_kernel_name(k)] = (ms / n, n, k)
+    _lib.ffst_profile_enable(0)
+    dom_name, (dom_avg_warm, _, dom_id) = max(per_kernel.items(), key=lambda kv: kv[1][0])
+    for _ in range(max(1, args.warmup // 2)):
+        step_plain()
+    torch.cuda.synchronize()
+    rec_err = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+
+    # timed region: batched form, dominant kernel bracketed by HIP events
+    _lib.ffst_profile_reset()
+    _lib.ffst_profile_enable(1 << dom_id)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_batched()
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    _lib.ffst_profile_enable(0)
+    dom_ms, dom_n = _lib.ffst_profile_read(dom_id)
+    dom_avg_ms = dom_ms / max(dom_n, 1)
+
+    # plain form on the same images
+    plain_steps = max(1, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        step_plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    coef_per_step = B * eta * M * N
+    value = coef_per_step * args.steps / t_batched / 1e9
+    value_plain = coef_per_step * plain_steps / t_plain / 1e9
+    ms_step = t_batched / args.steps * 1e3
+
+    # algorithmic bytes (per-unit figures are documented with the kernels)
+    lo, hi = plan.windows()
+    psi_half = plan.spectra(full_plane=False)
+    nnz_half = int((psi_half != 0).sum().item())
+    coef_bytes = 4 * coef_per_step
+    img_bytes = 4 * B * M * N
+    b_alg = 2 * coef_bytes + 2 * img_bytes + 2 * 4 * nnz_half
+    kernel_alg = {
+        "k_c2r_rows(planes)": coef_bytes,     # coefficients written
+        "k_r2c_rows(planes)": coef_bytes,     # coefficients read
+        "k_r2c_rows(image)": img_bytes,       # images read
+        "k_c2r_rows(image)": img_bytes,       # images written
+        "k_fwd_cols": 4 * nnz_half,           # nonzero spectrum values read
+        "k_adj_cols": 4 * nnz_half,
+    }
+    alg = kernel_alg.get(dom_name)
+    achieved = (alg / (dom_avg_ms * 1e-3) / 1e9) if alg else None
+    traffic = committed_traffic(dom_name, M, N, J, B)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcoef/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"FFST forward+adjoint, {B} cartoon images {M}x{N} per call, J={J} "
+                               f"({eta} spectra), batched form; plain form = 1 image per call",
+                   "M": M, "N": N, "J": J, "eta": eta, "batch": B, "parallelism": "single GPU"},
+        "plain": {"value": round(value_plain, 3), "unit": "Gcoef/s",
+                  "ms_per_step": round(t_plain / plain_steps * 1e3, 4),
+                  "batched_over_plain": round(value / value_plain, 3)},
+        "roofline": {"bound": "hbm", "kernel": dom_name,
+                     "achieved": round(achieved, 2) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": round(dom_avg_ms, 5),
+                     "launches_timed": dom_n},
+        "path_roofline": {"alg_bytes_per_step": b_alg,
+                          "achieved": round(b_alg / (ms_step * 1e-3) / 1e9, 2),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(b_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "nnz_half_spectra": nnz_half},
+        "kernels_warmup_avg_ms": {k: round(v[0], 5) for k, v in per_kernel.items()},
+        "check": {"reconstruction_rel_l2": rec_err},
+        "source_sha": source_hash(),
+    }
+
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        bcopy = torch.empty_like(a)
+        torch.cuda.synchronize()
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
+
+    plan.close()
+    del c, y, x
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(M, N, J, [imgs[i] for i in range(min(args.cpu_images, B))])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -18,7 +19,7 @@ struct ffst_plan {
   ffst_options opt{};
   double delta = 0.0;
   // device buffers owned by the plan
-  float* psi = nullptr;         // [eta][M][H]
+  float* psi = nullptr;         // [eta][H][M] (column-contiguous)
   float2* twM = nullptr;        // exp(-2 pi i m / M), m < M
   float2* twN = nullptr;        // exp(-2 pi i m / N), m < N
   int* d_lo = nullptr;          // per-plane window start, width, offset
@@ -27,14 +28,16 @@ struct ffst_plan {
   int* d_img_lo = nullptr;      // single full window for image-sized passes
   int* d_img_w = nullptr;
   long long* d_img_off = nullptr;
-  int2* d_items = nullptr;      // forward column tiles (spectrum, first column)
-  int* d_tile_ptr = nullptr;    // adjoint column tiles -> spectra (CSR)
-  int* d_tile_planes = nullptr;
+  int2* d_lines = nullptr;      // forward column lines (spectrum, column), by spectrum
+  int* d_col_ptr = nullptr;     // per plane group: columns -> spectra (CSR, absolute pointers)
+  int* d_col_planes = nullptr;
   // host copies
   std::vector<int> lo, w;
   std::vector<long long> off;
   long long zimg = 0;           // complex elements of one image's compact buffer
-  int nitems = 0, ntiles = 0;
+  std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
+  std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
+  long long chunk_elems = 0;    // target size of one unit's compact buffer
   unsigned magic = 0;
 };
 
@@ -60,8 +63,9 @@ bool plan_ok(const ffst_plan* p) { return p && p->magic == kMagic; }
 
 // ---- kernel timing -----------------------------------------------------
 const char* kKernelNames[KID_COUNT] = {
-    "k_spectra", "k_windows", "k_r2c_rows(image)", "k_fft_cols_image", "k_fwd_cols",
-    "k_c2r_rows(planes)", "k_r2c_rows(planes)", "k_adj_cols", "k_c2r_rows(image)", "k_expand"};
+    "k_spectra", "k_windows", "k_r2c_rows(image)", "k_col_fft(image)", "k_fwd_cols",
+    "k_c2r_rows(planes)", "k_r2c_rows(planes)", "k_adj_cols", "k_col_fft(inverse)",
+    "k_c2r_rows(image)", "k_expand"};
 
 struct ProfRec {
   int id;
@@ -149,7 +153,7 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
-                  p->d_img_off, p->d_items, p->d_tile_ptr, p->d_tile_planes};
+                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes};
   for (void* b : bufs)
     if (b) hipFree(b);
   p->magic = 0;
@@ -158,10 +162,45 @@ void free_plan(ffst_plan* p) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// How a call with `batch` images is cut into units of (images, plane group)
+// whose compact intermediate stays near the target size, and how the
+// adjoint's sum over spectra is spread over blocks.
+struct Schedule {
+  int chunk_imgs = 1;     // images per unit
+  int nparts = 1;         // adjoint partial sums per (image, tile)
+  bool fused = true;      // adjoint column pass ends with its inverse FFT
+  size_t fa_bytes = 0, yz_bytes = 0, part_bytes = 0;
+};
+
+Schedule schedule(const ffst_plan* p, int batch) {
+  Schedule sc;
+  const int ngroups = (int)p->groups.size() - 1;
+  long long max_group = 0;
+  for (int g = 0; g < ngroups; ++g)
+    max_group = std::max(max_group, p->off[p->groups[g + 1] - 1] + (long long)p->M * p->w[p->groups[g + 1] - 1] -
+                                        p->off[p->groups[g]]);
+  if (ngroups == 1 && p->zimg > 0)
+    sc.chunk_imgs = (int)std::max(1LL, std::min<long long>(batch, p->chunk_elems / std::max(1LL, p->zimg)));
+  // row kernels index rows and images with 32-bit integers
+  const long long rows_per_img = (long long)p->eta * p->M;
+  sc.chunk_imgs = (int)std::max(1LL, std::min<long long>(sc.chunk_imgs, (1LL << 30) / rows_per_img));
+  sc.chunk_imgs = std::max(1, std::min(sc.chunk_imgs, std::max(batch, 1)));
+  // adjoint column lines per unit; below ~2 lines per SIMD the spectra of a
+  // column are split over several lines (partial sums)
+  const long long units = (long long)p->H * sc.chunk_imgs;
+  const long long want = 8LL * 256;
+  sc.nparts = (int)std::min<long long>(8, std::max<long long>(1, (want + units - 1) / units));
+  sc.fused = (ngroups == 1 && sc.nparts == 1);
+  sc.fa_bytes = align256((size_t)batch * p->M * p->H * sizeof(float2));
+  sc.yz_bytes = align256((size_t)sc.chunk_imgs * (size_t)max_group * sizeof(float2));
+  sc.part_bytes = sc.fused ? 0 : align256((size_t)sc.nparts * sc.chunk_imgs * p->M * p->H * sizeof(float2));
+  return sc;
+}
+
 size_t ws_bytes(const ffst_plan* p, int batch) {
-  const size_t fa = align256((size_t)batch * p->M * p->H * sizeof(float2));
-  const size_t yz = align256((size_t)batch * (size_t)p->zimg * sizeof(float2));
-  return fa + yz;
+  if (batch <= 0) return 0;
+  const Schedule sc = schedule(p, batch);
+  return sc.fa_bytes + sc.yz_bytes + sc.part_bytes;
 }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -274,10 +313,10 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   }
 
   // Compact per-plane windows and the work lists of the column kernels.
-  const int TW = col_tile_width(M);
   p->w.assign(p->eta, 0);
   p->off.assign(p->eta, 0);
-  std::vector<int2> items;
+  p->line_ptr.assign(p->eta + 1, 0);
+  std::vector<int2> lines;
   long long acc = 0;
   for (int i = 0; i < p->eta; ++i) {
     if (hi[i] < p->lo[i]) {  // all-zero plane
@@ -288,25 +327,52 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     }
     p->off[i] = acc;
     acc += (long long)M * p->w[i];
-    for (int c0 = p->lo[i]; c0 < p->lo[i] + p->w[i]; c0 += TW) items.push_back(make_int2(i, c0));
+    p->line_ptr[i] = (int)lines.size();
+    for (int c = p->lo[i]; c < p->lo[i] + p->w[i]; ++c) lines.push_back(make_int2(i, c));
   }
+  p->line_ptr[p->eta] = (int)lines.size();
   p->zimg = acc;
-  p->nitems = (int)items.size();
-  p->ntiles = (p->H + TW - 1) / TW;
-  std::vector<int> tile_ptr(p->ntiles + 1, 0), tile_planes;
-  for (int t = 0; t < p->ntiles; ++t) {
-    const int a = t * TW, b = a + TW;
-    for (int i = 0; i < p->eta; ++i)
-      if (p->w[i] > 0 && p->lo[i] < b && p->lo[i] + p->w[i] > a) tile_planes.push_back(i);
-    tile_ptr[t + 1] = (int)tile_planes.size();
+
+  // Plane groups: consecutive spectra whose compact buffer for one image
+  // stays within the unit target (one group unless a single image is large).
+  const char* env = std::getenv("FFST_CHUNK_MB");
+  const long long chunk_mb = env ? std::max(1LL, std::atoll(env)) : 1024LL;
+  p->chunk_elems = chunk_mb * (1LL << 20) / (long long)sizeof(float2);
+  p->groups = {0};
+  long long gsize = 0;
+  for (int i = 0; i < p->eta; ++i) {
+    const long long sz = (long long)M * p->w[i];
+    if (gsize > 0 && gsize + sz > p->chunk_elems) {
+      p->groups.push_back(i);
+      gsize = 0;
+    }
+    gsize += sz;
+  }
+  p->groups.push_back(p->eta);
+  const int ngroups = (int)p->groups.size() - 1;
+  // Within a group, order the forward lines by column so that the lines that
+  // read the same column of F run next to each other.
+  for (int g = 0; g < ngroups; ++g)
+    std::stable_sort(lines.begin() + p->line_ptr[p->groups[g]], lines.begin() + p->line_ptr[p->groups[g + 1]],
+                     [](const int2& a, const int2& b) { return a.y < b.y; });
+
+  // Adjoint: column -> spectra whose window holds it, one CSR per plane group.
+  std::vector<int> col_ptr, col_planes;
+  for (int g = 0; g < ngroups; ++g) {
+    col_ptr.push_back((int)col_planes.size());
+    for (int c = 0; c < p->H; ++c) {
+      for (int i = p->groups[g]; i < p->groups[g + 1]; ++i)
+        if (p->w[i] > 0 && c >= p->lo[i] && c < p->lo[i] + p->w[i]) col_planes.push_back(i);
+      col_ptr.push_back((int)col_planes.size());
+    }
   }
   std::vector<int> img_lo{0}, img_w{p->H};
   std::vector<long long> img_off{0};
   if ((e = upload(&p->d_lo, p->lo)) != hipSuccess || (e = upload(&p->d_w, p->w)) != hipSuccess ||
       (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
-      (e = upload(&p->d_items, items)) != hipSuccess || (e = upload(&p->d_tile_ptr, tile_ptr)) != hipSuccess ||
-      (e = upload(&p->d_tile_planes, tile_planes)) != hipSuccess) {
+      (e = upload(&p->d_lines, lines)) != hipSuccess || (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
+      (e = upload(&p->d_col_planes, col_planes)) != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
@@ -332,13 +398,9 @@ int ffst_get_spectra(const ffst_plan* p, float* dst, int full_plane) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (!dst) return fail(FFST_EINVAL, "dst must be non-NULL");
   if (full_plane != 0 && full_plane != 1) return fail(FFST_EINVAL, "full_plane must be 0 or 1");
-  hipError_t e;
-  if (!full_plane) {
-    e = hipMemcpy(dst, p->psi, (size_t)p->eta * p->M * p->H * sizeof(float), hipMemcpyDeviceToDevice);
-  } else {
-    e = timed(KID_EXPAND, nullptr, [&] { return launch_expand(p->psi, p->M, p->N, p->eta, dst, nullptr); });
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-  }
+  const int cols = full_plane ? p->N : p->H;
+  hipError_t e = timed(KID_EXPAND, nullptr, [&] { return launch_expand(p->psi, p->M, p->N, p->eta, cols, dst, nullptr); });
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   return launched(e, "ffst_get_spectra");
 }
 
@@ -359,26 +421,37 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
                       batch, ws);
   if (st != FFST_OK || batch == 0) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const Schedule sc = schedule(p, batch);
   float2* F = static_cast<float2*>(ws);
-  float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) +
-                                        align256((size_t)batch * p->M * p->H * sizeof(float2)));
-  const long long M = p->M;
+  float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
+  const long long MH = (long long)p->M * p->H;
+  const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
-  hipError_t e = timed(KID_R2C_IMAGE, s, [&] {
-    return launch_r2c_rows(p->N, f, batch * M, p->M, 1, F, M * p->H, image_window(p), p->twN, s);
-  });
+
+  // F = fft2(f) on the half plane, column-contiguous
+  RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, image_window(p), p->twN};
+  hipError_t e = timed(KID_R2C_IMAGE, s, [&] { return launch_r2c_rows(ra, s); });
   if (e == hipSuccess)
-    e = timed(KID_FFT_COLS_IMAGE, s, [&] { return launch_fft_cols_image(p->M, p->N, F, batch, p->twM, s); });
-  if (e == hipSuccess && p->nitems > 0)
-    e = timed(KID_FWD_COLS, s, [&] {
-      return launch_fwd_cols(p->M, p->N, F, p->psi, batch, p->d_items, p->nitems, plane_windows(p), p->zimg, Y,
-                             scale, p->twM, s);
-    });
-  if (e == hipSuccess)
-    e = timed(KID_C2R_PLANES, s, [&] {
-      return launch_c2r_rows(p->N, Y, p->zimg, plane_windows(p), (long long)batch * p->eta * M, p->M, p->eta,
-                             coeffs, 1.0f, p->twN, s);
-    });
+    e = timed(KID_FFT_COLS_IMAGE, s,
+              [&] { return launch_line_fft(p->M, F, batch * p->H, false, nullptr, 0, 0, p->twM, s); });
+
+  const int ngroups = (int)p->groups.size() - 1;
+  for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
+    const int nimg = std::min(sc.chunk_imgs, batch - img0);
+    for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
+      const int p0 = p->groups[g], p1 = p->groups[g + 1];
+      const long long base = p->off[p0];
+      const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
+      FwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psi, p->d_lines + p->line_ptr[p0],
+                     p->line_ptr[p1] - p->line_ptr[p0], nimg, plane_windows(p), unit_stride, base, Y, scale,
+                     p->twM};
+      e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_lines(fa, s); });
+      if (e != hipSuccess) break;
+      RowArgs rc{coeffs + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
+                 p->M, p->N, plane_windows(p), p->twN};
+      e = timed(KID_C2R_PLANES, s, [&] { return launch_c2r_rows(rc, s); });
+    }
+  }
   return launched(e, "ffst_forward");
 }
 
@@ -389,24 +462,40 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
                       batch, ws);
   if (st != FFST_OK || batch == 0) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const Schedule sc = schedule(p, batch);
   float2* A = static_cast<float2*>(ws);
-  float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) +
-                                        align256((size_t)batch * p->M * p->H * sizeof(float2)));
-  const long long M = p->M;
+  float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
+  float2* P = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes + sc.yz_bytes);
+  const long long MH = (long long)p->M * p->H;
+  const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
-  hipError_t e = timed(KID_R2C_PLANES, s, [&] {
-    return launch_r2c_rows(p->N, coeffs, (long long)batch * p->eta * M, p->M, p->eta, Z, p->zimg,
-                           plane_windows(p), p->twN, s);
-  });
-  if (e == hipSuccess)
-    e = timed(KID_ADJ_COLS, s, [&] {
-      return launch_adj_cols(p->M, p->N, Z, p->zimg, plane_windows(p), p->psi, batch, p->d_tile_ptr,
-                             p->d_tile_planes, p->ntiles, A, scale, p->twM, s);
-    });
-  if (e == hipSuccess)
-    e = timed(KID_C2R_IMAGE, s, [&] {
-      return launch_c2r_rows(p->N, A, M * p->H, image_window(p), batch * M, p->M, 1, f, 1.0f, p->twN, s);
-    });
+  const int ngroups = (int)p->groups.size() - 1;
+  hipError_t e = hipSuccess;
+  for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
+    const int nimg = std::min(sc.chunk_imgs, batch - img0);
+    for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
+      const int p0 = p->groups[g], p1 = p->groups[g + 1];
+      const long long base = p->off[p0];
+      const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
+      RowArgs rr{const_cast<float*>(coeffs) + img0 * p->eta * MN, Z, p->eta * MN, unit_stride, base, nimg,
+                 p1 - p0, p0, p->M, p->N, plane_windows(p), p->twN};
+      e = timed(KID_R2C_PLANES, s, [&] { return launch_r2c_rows(rr, s); });
+      if (e != hipSuccess) break;
+      AdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psi,
+                     p->d_col_ptr + g * (p->H + 1), p->d_col_planes, nimg, sc.nparts, g > 0 ? 1 : 0,
+                     sc.fused ? 1 : 0, sc.fused ? A + img0 * MH : P, scale, p->twM};
+      e = timed(KID_ADJ_COLS, s, [&] { return launch_adj_lines(aa, s); });
+    }
+    if (e == hipSuccess && !sc.fused)
+      e = timed(KID_IFFT_COLS_IMAGE, s, [&] {
+        return launch_line_fft(p->M, A + img0 * MH, nimg * p->H, true, P, sc.nparts, (long long)nimg * MH,
+                               p->twM, s);
+      });
+  }
+  if (e == hipSuccess) {
+    RowArgs rc{f, A, MN, MH, 0, batch, 1, 0, p->M, p->N, image_window(p), p->twN};
+    e = timed(KID_C2R_IMAGE, s, [&] { return launch_c2r_rows(rc, s); });
+  }
   return launched(e, "ffst_adjoint");
 }
 

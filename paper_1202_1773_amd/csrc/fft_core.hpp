@@ -3,21 +3,26 @@
 // A length-L transform is carried by a "group" of G = L / V lanes; every lane
 // holds V complex values in registers, lane j holding element j + G*s in slot
 // s (s = 0 .. V-1). That layout is the same before and after the transform,
-// so a group loads and stores with unit stride across lanes (coalesced for
-// rows, tile-interleaved for columns).
+// so a group loads and stores with unit stride across lanes.
 //
 // Each stage is a radix-R Stockham autosort step (R = V, and one final
 // smaller radix when L is not a power of V). A lane runs V/R butterflies per
-// stage; butterfly b reads elements b + t*L/R, twiddles them by
+// stage; butterfly b reads elements b + t*L/R, multiplies them by the twiddles
 // W_{pR}^{t (b mod p)} (p = product of the earlier radices), applies the
 // R-point DFT in registers and writes element (b/p)*p*R + (b mod p) + t*p.
 // Between stages the values travel through LDS; after the last stage they
-// are back in the lane layout above, in natural order. Twiddles come from a
-// table tw[m] = exp(-2 pi i m / (L*ts)) (float32, rounded from float64 on the
-// host), read with stride ts.
+// are back in the lane layout above, in natural order.
 //
-// Every thread of the block must call these functions the same number of
-// times (they contain block barriers).
+// The twiddles a lane needs depend only on its lane index j, so they are read
+// once from a float32 table (rounded from float64 on the host) into
+// registers (TwiddleRegs) and reused for every transform the lane runs.
+//
+// Exchange synchronisation: when the whole group sits inside one wavefront
+// (Sync = kWave) the exchange only needs the LDS accesses of the wave to stay
+// in program order, which the hardware guarantees; a compiler barrier keeps
+// the compiler from reordering them. Otherwise (Sync = kBlock) block barriers
+// are used and every thread of the block must call the transform the same
+// number of times.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +33,10 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
@@ -115,7 +124,7 @@ struct Dft<16, INV> {
     // o[k] *= exp(-+ 2 pi i k / 16)
     constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
     constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
-    const float sg = INV ? 1.0f : -1.0f;
+    constexpr float sg = INV ? 1.0f : -1.0f;
     o[1] = cmul(o[1], make_float2(c1, sg * s1));
     o[2] = rot45<INV>(o[2]);
     o[3] = cmul(o[3], make_float2(s1, sg * c1));
@@ -131,30 +140,99 @@ struct Dft<16, INV> {
   }
 };
 
-// LDS index with one padding slot per 8 complex values (spreads the
-// power-of-two strides of the Stockham writes over the banks).
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int lds_len(int L) { return L + (L >> 3) + 1; }
+// ----------------------------------------------------------- radix plan
 
-template <int L, int V, int R, int P, bool LAST, bool INV>
-__device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* lds,
-                                               const float2* __restrict__ tw, int ts) {
-  constexpr int G = L / V;
-  constexpr int NB = V / R;
-  constexpr int TSTEP = L / (P * R);
+// Radices for length L with V values per lane: V, V, ..., then L / V^n.
+template <int L, int V>
+struct RadixPlan {
+  static_assert(L % V == 0 || L < V, "V must divide L");
+  static constexpr int G = L / V;
+  static constexpr int radix(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= ((L / p) % V == 0 ? V : L / p);
+    return (L / p) % V == 0 ? V : L / p;
+  }
+  static constexpr int span(int s) {  // product of the radices before stage s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i);
+    return p;
+  }
+  static constexpr int stages() {
+    int n = 0;
+    for (int p = 1; p < L; p *= radix(n), ++n) {
+    }
+    return n;
+  }
+  // offset of stage s's twiddles inside the per-lane register table
+  static constexpr int tw_offset(int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += (V / radix(i)) * (radix(i) - 1);
+    return o;
+  }
+  static constexpr int NTW = tw_offset(stages());
+};
+
+// Per-lane twiddles of all stages after the first (forward sign; the inverse
+// uses the conjugates). table[m] = exp(-2 pi i m / (L * ts)).
+template <int L, int V>
+struct TwiddleRegs {
+  using P = RadixPlan<L, V>;
+  float2 w[P::NTW > 0 ? P::NTW : 1];
+
+  template <int S>
+  __device__ __forceinline__ void load_stage(int j, const float2* __restrict__ table, int ts) {
+    if constexpr (S < P::stages()) {
+      constexpr int R = P::radix(S), SP = P::span(S), NB = V / R, TSTEP = L / (SP * R);
+      constexpr int OFF = P::tw_offset(S);
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        const int k = (j + m * P::G) % SP;
+#pragma unroll
+        for (int t = 1; t < R; ++t) w[OFF + m * (R - 1) + t - 1] = table[(t * k * TSTEP) * ts];
+      }
+      load_stage<S + 1>(j, table, ts);
+    }
+  }
+  __device__ __forceinline__ void load(int j, const float2* __restrict__ table, int ts) {
+    load_stage<1>(j, table, ts);
+  }
+};
+
+enum SyncKind { kWave = 0, kBlock = 1 };
+
+template <int SYNC>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (SYNC == kBlock) {
+    __syncthreads();
+  } else {
+    // LDS accesses of one wavefront complete in program order; only the
+    // compiler has to be kept from moving them across this point.
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
+  }
+}
+
+// LDS index with one padding slot per V complex values.
+template <int V>
+__device__ __forceinline__ int lpad(int i) {
+  return i + i / V;
+}
+
+template <int L, int V, int S, bool INV, int SYNC>
+__device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* lds, const TwiddleRegs<L, V>& tw) {
+  using P = RadixPlan<L, V>;
+  constexpr int G = P::G, R = P::radix(S), SP = P::span(S), NB = V / R, OFF = P::tw_offset(S);
+  constexpr bool LAST = (S + 1 == P::stages());
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
-    const int b = j + m * G;
-    const int k = b % P;
     float2 a[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) a[t] = u[m + t * NB];
-    if constexpr (P > 1) {
+    if constexpr (S > 0) {
 #pragma unroll
       for (int t = 1; t < R; ++t) {
-        float2 w = tw[(t * k * TSTEP) * ts];
-        if constexpr (INV) w.y = -w.y;
-        a[t] = cmul(a[t], w);
+        const float2 w = tw.w[OFF + m * (R - 1) + t - 1];
+        a[t] = INV ? cmulc(a[t], w) : cmul(a[t], w);
       }
     }
     Dft<R, INV>::run(a);
@@ -162,41 +240,33 @@ __device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* ld
 #pragma unroll
       for (int t = 0; t < R; ++t) u[m + t * NB] = a[t];
     } else {
-      const int base = (b / P) * P * R + k;
+      const int b = j + m * G;
+      const int base = (b / SP) * SP * R + (b % SP);
 #pragma unroll
-      for (int t = 0; t < R; ++t) lds[lpad(base + t * P)] = a[t];
+      for (int t = 0; t < R; ++t) lds[lpad<V>(base + t * SP)] = a[t];
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    lds_sync<SYNC>();
 #pragma unroll
-    for (int s = 0; s < V; ++s) u[s] = lds[lpad(j + G * s)];
-    __syncthreads();
+    for (int s = 0; s < V; ++s) u[s] = lds[lpad<V>(j + G * s)];
+    lds_sync<SYNC>();
+    stockham_stage<L, V, S + 1, INV, SYNC>(u, j, lds, tw);
   }
 }
-
-template <int L, int V, int P, bool INV>
-struct Stages {
-  static __device__ __forceinline__ void run(float2 (&u)[V], int j, float2* lds,
-                                             const float2* __restrict__ tw, int ts) {
-    constexpr int REM = L / P;
-    constexpr int R = (REM % V == 0) ? V : REM;
-    static_assert(V % R == 0, "final radix must divide the values per lane");
-    constexpr bool LAST = (P * R == L);
-    stockham_stage<L, V, R, P, LAST, INV>(u, j, lds, tw, ts);
-    if constexpr (!LAST) Stages<L, V, P * R, INV>::run(u, j, lds, tw, ts);
-  }
-};
 
 // In-place length-L FFT of the group's values (forward: kernel exp(-2 pi i nk/L),
 // inverse: exp(+2 pi i nk/L), both unnormalised).
-template <int L, int V, bool INV>
-__device__ __forceinline__ void fft_group(float2 (&u)[V], int j, float2* lds,
-                                          const float2* __restrict__ tw, int ts) {
-  Stages<L, V, 1, INV>::run(u, j, lds, tw, ts);
+template <int L, int V, bool INV, int SYNC>
+__device__ __forceinline__ void fft_group(float2 (&u)[V], int j, float2* lds, const TwiddleRegs<L, V>& tw) {
+  stockham_stage<L, V, 0, INV, SYNC>(u, j, lds, tw);
 }
 
-// Values per lane used for a transform of length L.
-__host__ __device__ constexpr int values_per_lane(int L) { return L >= 2048 ? 16 : (L >= 8 ? 8 : L); }
+// Complex elements of LDS a group needs (padded indices stay below this).
+__host__ __device__ constexpr int lds_group_len(int L, int V) { return L + L / V + 1; }
+
+// Smallest stride >= n that is congruent to r modulo 32 (in complex elements);
+// used to spread the groups of one half-wavefront over all LDS banks.
+__host__ __device__ constexpr int stride_mod32(int n, int r) { return n + ((r - n % 32) % 32 + 32) % 32; }
 
 }  // namespace ffst

@@ -33,6 +33,7 @@ enum KernelId : int {
   KID_C2R_PLANES,
   KID_R2C_PLANES,
   KID_ADJ_COLS,
+  KID_IFFT_COLS_IMAGE,
   KID_C2R_IMAGE,
   KID_EXPAND,
   KID_COUNT
@@ -42,26 +43,59 @@ enum KernelId : int {
 hipError_t launch_spectra(const GenParams& g, int eta, const int* kind, const int* jj, const int* kk,
                           float* psi, hipStream_t s);
 hipError_t launch_windows(const float* psi, int M, int N, int eta, int* lo, int* hi, hipStream_t s);
-hipError_t launch_expand(const float* psi, int M, int N, int eta, float* out, hipStream_t s);
+hipError_t launch_expand(const float* psi, int M, int N, int eta, int cols, float* out, hipStream_t s);
 
-// Row transforms of length N = 2L along contiguous rows.
-// rows are enumerated as ((img * planes) + p) * M + r.
-hipError_t launch_r2c_rows(int N, const float* x, long long nrows, int M, int planes, float2* out,
-                           long long img_stride, Windows win, const float2* twN, hipStream_t s);
-hipError_t launch_c2r_rows(int N, const float2* in, long long img_stride, Windows win, long long nrows,
-                           int M, int planes, float* y, float scale, const float2* twN, hipStream_t s);
+// Row transforms of length N = 2L. The rows of a unit are (img, plane, r) for
+// img < nimg, plane0 <= plane < plane0 + nplanes, r < M; real row
+// (img, plane, r) starts at x + img*x_img_stride + (plane*M + r)*N. The
+// complex side is column-contiguous: column c of (img, plane) holds M values
+// at z + img*z_img_stride + (win.off[plane] - z_off_base) + (c - lo)*M, for
+// the half-plane columns c in [lo, lo + w) of the plane's window.
+struct RowArgs {
+  float* x;
+  float2* z;
+  long long x_img_stride, z_img_stride, z_off_base;
+  int nimg, nplanes, plane0, M, N;
+  Windows win;
+  const float2* twN;
+};
+hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s);
+hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s);
 
-// Column transforms of length M over the half plane (N/2 + 1 columns).
-hipError_t launch_fft_cols_image(int M, int N, float2* F, int batch, const float2* twM, hipStream_t s);
-hipError_t launch_fwd_cols(int M, int N, const float2* F, const float* psi, int batch, const int2* items,
-                           int nitems, Windows win, long long img_stride, float2* Y, float scale,
-                           const float2* twM, hipStream_t s);
-hipError_t launch_adj_cols(int M, int N, const float2* Z, long long img_stride, Windows win,
-                           const float* psi, int batch, const int* tile_ptr, const int* tile_planes,
-                           int ntiles, float2* A, float scale, const float2* twM, hipStream_t s);
+// In-place FFT of nlines contiguous lines of length M; the inverse may first
+// replace each line by the sum of the same line in `nparts` partial arrays.
+hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const float2* parts, int nparts,
+                           long long part_stride, const float2* twM, hipStream_t s);
 
-// Columns per column-kernel tile for a transform length M.
-int col_tile_width(int M);
+struct FwdLineArgs {
+  int M, N;
+  const float2* F;          // [nimg][N/2+1][M]
+  const float* psi;         // [eta][N/2+1][M]
+  const int2* lines;        // (spectrum, column)
+  int nlines, nimg;
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s);
+
+struct AdjLineArgs {
+  int M, N;
+  const float2* Z;
+  long long z_img_stride, z_off_base;
+  Windows win;
+  const float* psi;
+  const int* col_ptr;
+  const int* col_planes;
+  int nimg, nparts, accumulate, fused;
+  float2* out;
+  float scale;
+  const float2* twM;
+};
+hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s);
+
 bool supported_length(int L);
 
 }  // namespace ffst

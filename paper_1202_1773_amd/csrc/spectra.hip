@@ -3,7 +3,8 @@
 //
 // Grid (Sec. 3.5.1): omega_1 = Delta * q_N(c) along columns, omega_2 =
 // Delta * q_M(r) along rows, q_D(p) = p for p <= ceil(D/2) - 1 and p - D
-// otherwise (natural DFT order). Only the half plane c = 0 .. N/2 is stored.
+// otherwise (natural DFT order). Only the half plane c = 0 .. N/2 is stored,
+// column-contiguous: psi[i][c][r] (the layout the column passes stream).
 //
 // Windows (Sec. 2.1, 2.4, 3.4):
 //   v(x)      = x^4 (35 - 84 x + 70 x^2 - 20 x^3) on [0, 1], clamped outside
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(256) k_spectra(GenParams g, const int* __restr
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (idx >= n) return;
-  const int r = (int)(idx / H), c = (int)(idx % H);
+  const int c = (int)(idx / g.M), r = (int)(idx % g.M);
   const int kd = kind[i], j = jj[i], k = kk[i];
   double val = grid_value(g, kd, j, k, r, c);
   if (g.N % 2 == 0 && c == g.N / 2) {
@@ -113,33 +114,34 @@ __global__ void __launch_bounds__(256) k_spectra(GenParams g, const int* __restr
   psi[(long long)i * n + idx] = (float)val;
 }
 
-// First and last half-plane column holding a nonzero value, per plane.
+// First and last half-plane column holding a nonzero value, per plane:
+// one block per (column, plane) line.
 __global__ void __launch_bounds__(256) k_windows(const float* __restrict__ psi, int M, int H,
                                                  int* __restrict__ lo, int* __restrict__ hi) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x;
   const int i = blockIdx.y;
-  if (c >= H) return;
-  const float* p = psi + (long long)i * M * H + c;
-  bool any = false;
-  for (int r = 0; r < M && !any; ++r) any = p[(long long)r * H] != 0.0f;
-  if (any) {
+  const float* p = psi + ((long long)i * H + c) * M;
+  int any = 0;
+  for (int r = threadIdx.x; r < M; r += blockDim.x) any |= (p[r] != 0.0f);
+  if (__syncthreads_or(any) && threadIdx.x == 0) {
     atomicMin(lo + i, c);
     atomicMax(hi + i, c);
   }
 }
 
-// Full-plane copy: columns beyond N/2 by evenness on the grid.
-__global__ void __launch_bounds__(256) k_expand(const float* __restrict__ psi, int M, int N,
+// Row-major copy of the spectra: out[i][r][c] for c < cols (cols = N/2 + 1,
+// or N with the missing columns filled by evenness on the grid).
+__global__ void __launch_bounds__(256) k_expand(const float* __restrict__ psi, int M, int N, int cols,
                                                 float* __restrict__ out) {
   const int H = N / 2 + 1;
-  const long long n = (long long)M * N;
+  const long long n = (long long)M * cols;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (idx >= n) return;
-  const int r = (int)(idx / N), c = (int)(idx % N);
+  const int r = (int)(idx / cols), c = (int)(idx % cols);
   const int rr = c < H ? r : (M - r) % M;
   const int cc = c < H ? c : N - c;
-  out[(long long)i * n + idx] = psi[(long long)i * M * H + (long long)rr * H + cc];
+  out[(long long)i * n + idx] = psi[((long long)i * H + cc) * M + rr];
 }
 
 }  // namespace
@@ -154,15 +156,15 @@ hipError_t launch_spectra(const GenParams& g, int eta, const int* kind, const in
 
 hipError_t launch_windows(const float* psi, int M, int N, int eta, int* lo, int* hi, hipStream_t s) {
   const int H = N / 2 + 1;
-  dim3 grid((unsigned)((H + 255) / 256), (unsigned)eta);
+  dim3 grid((unsigned)H, (unsigned)eta);
   hipLaunchKernelGGL(k_windows, grid, dim3(256), 0, s, psi, M, H, lo, hi);
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const float* psi, int M, int N, int eta, float* out, hipStream_t s) {
-  const long long n = (long long)M * N;
+hipError_t launch_expand(const float* psi, int M, int N, int eta, int cols, float* out, hipStream_t s) {
+  const long long n = (long long)M * cols;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)eta);
-  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, s, psi, M, N, out);
+  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, s, psi, M, N, cols, out);
   return hipGetLastError();
 }
 

@@ -1,20 +1,29 @@
 // transform.hip -- the FFST hot path on gfx950.
 //
-// Forward (eq. shearletTransform): F = fft2(f) as a real-to-complex row pass
-// (k_r2c_rows) and an in-place column pass (k_fft_cols_image); then, per
-// spectrum i and tile of half-plane columns, k_fwd_cols loads the tile of F,
-// multiplies by Psi_i / (M N), runs the inverse column FFT and stores the
-// tile into a compact per-plane intermediate Y_i that only spans the
-// columns where Psi_i is nonzero; k_c2r_rows finishes each row with a
-// complex-to-real inverse FFT and writes the coefficients. Psi_i * F is never
-// stored.
+// Layouts. Every half-plane spectrum (columns c = 0 .. N/2 of a DFT) is kept
+// column-contiguous, [c][r]: the image spectrum F, the adjoint's sum A, the
+// spectra Psi_i, and the per-spectrum intermediates Y_i / Z_i, which only
+// hold the columns [lo_i, lo_i + w_i) where Psi_i is nonzero. The column-
+// direction FFTs then stream contiguous lines, and the row kernels move
+// between the two layouts through LDS, writing and reading 16 consecutive
+// rows of a column at a time (128-byte segments).
 //
-// Adjoint / inverse (eq. inverseShearletTransform): k_r2c_rows on every
-// coefficient row, keeping only the columns inside Psi_i's window (Z_i);
-// k_adj_cols loads, per tile of columns, the Z_i of every spectrum touching
-// the tile, runs the forward column FFT, multiplies by Psi_i and accumulates
-// in registers (the sum over (j, k)), then applies the inverse column FFT to
-// the sum; k_c2r_rows turns the result into the image.
+// Forward (eq. shearletTransform): k_r2c_rows turns the image rows into F
+// (real-to-complex along rows, transposed store); k_line_fft transforms F
+// along the columns; k_fwd_lines multiplies each column line of F by the
+// matching line of Psi_i / (M N), runs the inverse FFT along the column and
+// stores Y_i; k_c2r_rows reads Y_i back by row blocks and finishes every row
+// with a complex-to-real inverse FFT, writing the coefficients. Psi_i * F is
+// never stored.
+//
+// Adjoint / inverse (eq. inverseShearletTransform): k_r2c_rows on the
+// coefficient rows, storing only the window columns (Z_i); k_adj_lines runs,
+// per column line, the forward FFT of every Z_i that has the column,
+// multiplies by Psi_i and accumulates the sum over (j, k) in registers, then
+// applies the inverse column FFT to the sum (or, when the spectra are split
+// over several lines for parallelism, stores partial sums that k_line_fft
+// adds in a fixed order before its inverse FFT); k_c2r_rows returns to the
+// image.
 //
 // Real FFT of length N = 2L along a row: z[n] = x[2n] + i x[2n+1],
 // Z = FFT_L(z), X[k] = ((Z[k] + conj Z[L-k]) - i W_N^k (Z[k] - conj Z[L-k])) / 2
@@ -28,235 +37,438 @@
 namespace ffst {
 namespace {
 
-constexpr int kRowBlock = 256;
+__host__ __device__ constexpr int line_values(int L) { return L >= 16 ? 16 : L; }
+// LDS stride per line/row: congruent to 17 mod 32, so that 16 lanes reading
+// the same column of 16 rows, and 16 lanes reading 16 consecutive values of
+// one row, both touch distinct banks.
+__host__ __device__ constexpr int lds_stride(int L, int V) { return stride_mod32(lds_group_len(L, V), 17); }
 
+// Rows of length N = 2L, RB rows per block.
 template <int L>
 struct RowCfg {
-  static constexpr int V = values_per_lane(L);
-  static constexpr int G = L / V;
-  static constexpr int RB = kRowBlock / G;  // rows per block
-  static_assert(G <= kRowBlock, "row too long");
+  static constexpr int V = line_values(L);
+  static constexpr int G = L / V;                      // lanes per row
+  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
+  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 8;
+  static constexpr int THREADS = RB * G;
+  static constexpr int STRIDE = lds_stride(L, V);
 };
 
-template <int M>
-struct ColCfg {
-  static constexpr int V = values_per_lane(M);
-  static constexpr int G = M / V;
-  static constexpr int TW = (8 * G <= 1024) ? 8 : 1024 / G;  // columns per tile
-  static constexpr int THREADS = TW * G;
+// Contiguous lines of length L (the column direction, L = M).
+template <int L>
+struct LineCfg {
+  static constexpr int V = line_values(L);
+  static constexpr int G = L / V;
+  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
+  static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
+  static constexpr int LPB = THREADS / G;             // lines per block
+  static constexpr int STRIDE = lds_stride(L, V);
 };
 
 // ---------------------------------------------------------------- rows
 
-template <int L>
-__global__ void __launch_bounds__(kRowBlock) k_r2c_rows(const float* __restrict__ x, long long nrows, int M,
-                                                        int planes, float2* __restrict__ out,
-                                                        long long img_stride, Windows win,
-                                                        const float2* __restrict__ twN) {
-  using C = RowCfg<L>;
-  constexpr int V = C::V, G = C::G;
-  __shared__ float2 lds[C::RB * lds_len(L)];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
-  const long long row = (long long)blockIdx.x * C::RB + g;
-  const bool valid = row < nrows;
-  float2* my = lds + g * lds_len(L);
+struct RowJob {
+  float* x;                 // real rows: row (img, plane, r) at x + img*x_img_stride + (plane*M + r)*N
+  float2* z;                // compact columns: (img, plane, c, r) at z + img*z_img_stride +
+                            //   (win.off[plane] - z_off_base) + (c - lo)*M + r
+  long long x_img_stride, z_img_stride, z_off_base;
+  int nimg, nplanes, plane0, M, rb;   // rb = rows per block (divides M)
+  float inv_nplanes;
+  Windows win;
+  const float2* twN;        // exp(-2 pi i m / N), m < N
+};
 
-  float2 u[V];
-  const float2* xr = reinterpret_cast<const float2*>(x) + (valid ? row : 0) * (long long)L;
-#pragma unroll
-  for (int s = 0; s < V; ++s) u[s] = valid ? xr[j + G * s] : make_float2(0.f, 0.f);
+struct RowUnit {
+  int img, plane, r0;
+};
 
-  fft_group<L, V, false>(u, j, my, twN, 2);
-
-  // Z[L - k] for every k held by this lane.
-#pragma unroll
-  for (int s = 0; s < V; ++s) my[lpad(j + G * s)] = u[s];
-  __syncthreads();
-  float2 zm[V];
-#pragma unroll
-  for (int s = 0; s < V; ++s) zm[s] = my[lpad((L - (j + G * s)) % L)];
-  __syncthreads();
-
-  if (!valid) return;
-  const int r = (int)(row % M);
-  const long long pr = row / M;
-  const int p = (int)(pr % planes);
-  const long long img = pr / planes;
-  const int lo = win.lo[p], w = win.w[p];
-  float2* o = out + img * img_stride + win.off[p] + (long long)r * w;
-#pragma unroll
-  for (int s = 0; s < V; ++s) {
-    const int k = j + G * s;
-    if (k >= lo && k < lo + w) {
-      const float2 zc = conjf2(zm[s]);
-      const float2 a = cadd(u[s], zc);
-      const float2 b = cmul(twN[k], csub(u[s], zc));
-      o[k - lo] = cscale(csub(a, make_float2(-b.y, b.x)), 0.5f);
-    }
-  }
-  if (j == 0 && L >= lo && L < lo + w) o[L - lo] = make_float2(u[0].x - u[0].y, 0.f);
+__device__ __forceinline__ RowUnit row_unit(int u, int blocks_per_plane, int nplanes, float inv_nplanes, int rb,
+                                            int plane0) {
+  RowUnit ru;
+  const int pq = u / blocks_per_plane;
+  ru.r0 = (u - pq * blocks_per_plane) * rb;
+  ru.img = (int)(((float)pq + 0.5f) * inv_nplanes);  // exact for pq < 2^20
+  ru.plane = plane0 + pq - ru.img * nplanes;
+  return ru;
 }
 
-template <int L>
-__global__ void __launch_bounds__(kRowBlock) k_c2r_rows(const float2* __restrict__ in, long long img_stride,
-                                                        Windows win, long long nrows, int M, int planes,
-                                                        float* __restrict__ y, float scale,
-                                                        const float2* __restrict__ twN) {
+// SMALL: images with fewer than RB rows; the block then covers job.rb rows.
+//
+// Both row kernels are software-pipelined over the units a block visits: the
+// global loads of the next unit are issued before the current unit's FFT, so
+// their latency overlaps the arithmetic.
+template <int L, bool SMALL>
+__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
   using C = RowCfg<L>;
-  constexpr int V = C::V, G = C::G;
-  __shared__ float2 lds[C::RB * lds_len(L)];
+  constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  const int g = threadIdx.x / G;          // row slot (FFT phase)
+  const int j = threadIdx.x % G;
+  const int rb = SMALL ? job.rb : C::RB;
+  const int tr = threadIdx.x % rb;        // row (transpose phase)
+  const int tc = threadIdx.x / rb;        // first column (transpose phase)
+  const int cstep = NT / rb;
+  const bool row_ok = g < rb;
+  float2* my = lds + g * C::STRIDE;
+  TwiddleRegs<L, V> tw;
+  tw.load(j, job.twN, 2);
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+
+  auto load_rows = [&](int u, float2 (&dst)[V]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const float2* xr = reinterpret_cast<const float2*>(job.x + ru.img * job.x_img_stride +
+                                                       ((long long)ru.plane * job.M + ru.r0 + (row_ok ? g : 0)) * N);
+#pragma unroll
+    for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+  };
+
+  float2 nxt[V];
+  int u = blockIdx.x;
+  if (u < nunits) load_rows(u, nxt);
+  for (; u < nunits; u += gridDim.x) {
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = nxt[s];
+    if (u + (int)gridDim.x < nunits) load_rows(u + gridDim.x, nxt);
+    fft_group<L, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+    for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = v[s];
+    __syncthreads();
+
+    // X[c] = ((Z[c] + conj Z[L-c]) - i W_N^c (Z[c] - conj Z[L-c])) / 2 for the
+    // window columns, stored column-contiguous (rb consecutive rows per column).
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    float2* out = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+    const float2* zr = lds + tr * C::STRIDE;
+#pragma unroll 4
+    for (int c = lo + tc; c < lo + w; c += cstep) {
+      const float2 zc = zr[lpad<V>(c & (L - 1))];
+      const float2 zm = conjf2(zr[lpad<V>((L - c) & (L - 1))]);
+      const float2 a = cadd(zc, zm);
+      const float2 b = cmul(job.twN[c], csub(zc, zm));
+      out[(long long)(c - lo) * job.M] = make_float2(0.5f * (a.x + b.y), 0.5f * (a.y - b.x));
+    }
+    __syncthreads();
+  }
+}
+
+template <int L, bool SMALL>
+__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
+  using C = RowCfg<L>;
+  constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
+  // values each thread moves in the transposed load: k = tc + STEP m, k <= L
+  constexpr int STEP = NT / C::RB;
+  constexpr int NLD = L / STEP + 1;
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  __shared__ float2 wsh[L];               // W_N^k, k < L
   const int g = threadIdx.x / G;
   const int j = threadIdx.x % G;
-  const long long row = (long long)blockIdx.x * C::RB + g;
-  const bool valid = row < nrows;
-  float2* my = lds + g * lds_len(L);
+  const int rb = SMALL ? job.rb : C::RB;
+  const int tr = threadIdx.x % rb;
+  const int tc = threadIdx.x / rb;
+  float2* my = lds + g * C::STRIDE;
+  TwiddleRegs<L, V> tw;
+  tw.load(j, job.twN, 2);
+  for (int k = threadIdx.x; k < L; k += NT) wsh[k] = job.twN[k];
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+  float2* zr = lds + tr * C::STRIDE;
 
-  int lo = 0, w = 0;
-  const float2* ir = in;
-  if (valid) {
-    const int r = (int)(row % M);
-    const long long pr = row / M;
-    const int p = (int)(pr % planes);
-    const long long img = pr / planes;
-    lo = win.lo[p];
-    w = win.w[p];
-    ir = in + img * img_stride + win.off[p] + (long long)r * w;
-  }
-  float2 u[V];
+  // raw half-plane rows X[0 .. L] of a unit (zero outside the window), in
+  // the transposed mapping: thread (tr, tc) holds rows tr, columns tc + STEP m
+  auto load_cols = [&](int u, float2 (&dst)[NLD]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    const float2* in = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+    const int step = SMALL ? NT / rb : STEP;
 #pragma unroll
-  for (int s = 0; s < V; ++s) {
-    const int k = j + G * s;
-    const int km = L - k;
-    const float2 xk = (k >= lo && k < lo + w) ? ir[k - lo] : make_float2(0.f, 0.f);
-    const float2 xm = (km >= lo && km < lo + w) ? ir[km - lo] : make_float2(0.f, 0.f);
-    const float2 xc = conjf2(xm);
-    const float2 a = cadd(xk, xc);
-    const float2 b = cmul(conjf2(twN[k]), csub(xk, xc));
-    u[s] = cadd(a, make_float2(-b.y, b.x));
-  }
+    for (int m = 0; m < NLD; ++m) {
+      const int k = tc + step * m;
+      dst[m] = (k <= L && (unsigned)(k - lo) < (unsigned)w) ? in[(long long)(k - lo) * job.M] : make_float2(0.f, 0.f);
+    }
+  };
 
-  fft_group<L, V, true>(u, j, my, twN, 2);
-
-  if (!valid) return;
-  float2* yr = reinterpret_cast<float2*>(y) + row * (long long)L;
+  if constexpr (SMALL) {
+    // few rows: no pipelining, every thread may own more columns
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+      const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+      const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+      const float2* in = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+      for (int k = tc; k <= L; k += NT / rb)
+        zr[lpad<V>(k)] = (unsigned)(k - lo) < (unsigned)w ? in[(long long)(k - lo) * job.M] : make_float2(0.f, 0.f);
+      __syncthreads();
+      float2 v[V];
 #pragma unroll
-  for (int s = 0; s < V; ++s) yr[j + G * s] = cscale(u[s], scale);
+      for (int s = 0; s < V; ++s) {
+        const int k = j + G * s;
+        const float2 xk = my[lpad<V>(k)], xm = my[lpad<V>(L - k)];
+        const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
+        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
+        const float2 b = cmulc(d, wsh[k]);
+        v[s] = make_float2(a.x - b.y, a.y + b.x);
+      }
+      lds_sync<C::SYNC>();
+      fft_group<L, V, true, C::SYNC>(v, j, my, tw);
+      if (g < rb) {
+        float2* yr = reinterpret_cast<float2*>(job.x + ru.img * job.x_img_stride +
+                                               ((long long)ru.plane * job.M + ru.r0 + g) * N);
+#pragma unroll
+        for (int s = 0; s < V; ++s) yr[j + G * s] = v[s];
+      }
+      __syncthreads();
+    }
+  } else {
+    float2 nxt[NLD];
+    int u = blockIdx.x;
+    if (u < nunits) load_cols(u, nxt);
+    for (; u < nunits; u += gridDim.x) {
+#pragma unroll
+      for (int m = 0; m < NLD; ++m) {
+        const int k = tc + STEP * m;
+        if (k <= L) zr[lpad<V>(k)] = nxt[m];
+      }
+      __syncthreads();
+      if (u + (int)gridDim.x < nunits) load_cols(u + gridDim.x, nxt);
+      // Z'[k] = (X[k] + conj X[L-k]) + i conj(W_N^k) (X[k] - conj X[L-k])
+      float2 v[V];
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        const int k = j + G * s;
+        const float2 xk = my[lpad<V>(k)], xm = my[lpad<V>(L - k)];
+        const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
+        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
+        const float2 b = cmulc(d, wsh[k]);
+        v[s] = make_float2(a.x - b.y, a.y + b.x);
+      }
+      lds_sync<C::SYNC>();
+      fft_group<L, V, true, C::SYNC>(v, j, my, tw);
+      const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+      float2* yr = reinterpret_cast<float2*>(job.x + ru.img * job.x_img_stride +
+                                             ((long long)ru.plane * job.M + ru.r0 + g) * N);
+#pragma unroll
+      for (int s = 0; s < V; ++s) yr[j + G * s] = v[s];
+      __syncthreads();
+    }
+  }
 }
 
 // ------------------------------------------------------------- columns
 
-// F[b] (M x H, H = N/2 + 1) in place: forward FFT along each column.
-template <int M>
-__global__ void __launch_bounds__(ColCfg<M>::THREADS) k_fft_cols_image(float2* __restrict__ F, int H,
-                                                                       const float2* __restrict__ twM) {
-  using C = ColCfg<M>;
-  constexpr int V = C::V, G = C::G, TW = C::TW;
-  __shared__ float2 lds[TW * lds_len(M)];
-  const int col = threadIdx.x % TW;
-  const int j = threadIdx.x / TW;
-  const int c = blockIdx.x * TW + col;
-  const bool valid = c < H;
-  float2* base = F + (long long)blockIdx.y * M * H + c;
-  float2 u[V];
+// In-place FFT of nlines contiguous lines of length M. Inverse with nparts > 0:
+// each line is first replaced by the sum of the same line of `nparts`
+// partial arrays (parts + p * part_stride), added in order p = 0, 1, ...
+template <int M, bool INV>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines,
+                                                                  const float2* __restrict__ parts, int nparts,
+                                                                  long long part_stride,
+                                                                  const float2* __restrict__ twM) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, twM, 1);
+  for (int u = blockIdx.x; u * C::LPB < nlines; u += gridDim.x) {
+    const int line = u * C::LPB + g;
+    const bool ok = line < nlines;
+    float2* base = F + (long long)(ok ? line : 0) * M;
+    float2 v[V];
+    if (nparts > 0) {
 #pragma unroll
-  for (int s = 0; s < V; ++s) u[s] = valid ? base[(long long)(j + G * s) * H] : make_float2(0.f, 0.f);
-  fft_group<M, V, false>(u, j, lds + col * lds_len(M), twM, 1);
-  if (!valid) return;
+      for (int s = 0; s < V; ++s) v[s] = make_float2(0.f, 0.f);
+      for (int p = 0; p < nparts; ++p) {
+        const float2* pb = parts + p * part_stride + (long long)(ok ? line : 0) * M;
 #pragma unroll
-  for (int s = 0; s < V; ++s) base[(long long)(j + G * s) * H] = u[s];
-}
-
-// One (image, spectrum, column tile) per block: Y_i = ifft_col(Psi_i * scale * F).
-template <int M>
-__global__ void __launch_bounds__(ColCfg<M>::THREADS) k_fwd_cols(const float2* __restrict__ F,
-                                                                 const float* __restrict__ psi, int H,
-                                                                 int batch, const int2* __restrict__ items,
-                                                                 Windows win, long long img_stride,
-                                                                 float2* __restrict__ Y, float scale,
-                                                                 const float2* __restrict__ twM) {
-  using C = ColCfg<M>;
-  constexpr int V = C::V, G = C::G, TW = C::TW;
-  __shared__ float2 lds[TW * lds_len(M)];
-  const int col = threadIdx.x % TW;
-  const int j = threadIdx.x / TW;
-  const int item = blockIdx.x / batch;
-  const int b = blockIdx.x % batch;
-  const int2 it = items[item];  // (spectrum, first column of the tile)
-  const int i = it.x;
-  const int c = it.y + col;
-  const int lo = win.lo[i], w = win.w[i];
-  const bool valid = c < lo + w;
-  const float2* fb = F + (long long)b * M * H + c;
-  const float* pb = psi + (long long)i * M * H + c;
-  float2 u[V];
+        for (int s = 0; s < V; ++s) v[s] = cadd(v[s], pb[j + G * s]);
+      }
+    } else {
 #pragma unroll
-  for (int s = 0; s < V; ++s) {
-    const long long off = (long long)(j + G * s) * H;
-    u[s] = valid ? cscale(fb[off], pb[off] * scale) : make_float2(0.f, 0.f);
-  }
-  fft_group<M, V, true>(u, j, lds + col * lds_len(M), twM, 1);
-  if (!valid) return;
-  float2* yb = Y + (long long)b * img_stride + win.off[i] + (c - lo);
+      for (int s = 0; s < V; ++s) v[s] = base[j + G * s];
+    }
+    fft_group<M, V, INV, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
+    if (ok) {
 #pragma unroll
-  for (int s = 0; s < V; ++s) yb[(long long)(j + G * s) * w] = u[s];
-}
-
-// One (image, column tile) per block: A = scale * ifft_col( sum_i Psi_i * fft_col(Z_i) ).
-template <int M>
-__global__ void __launch_bounds__(ColCfg<M>::THREADS) k_adj_cols(const float2* __restrict__ Z,
-                                                                 long long img_stride, Windows win,
-                                                                 const float* __restrict__ psi, int H,
-                                                                 int batch, const int* __restrict__ tile_ptr,
-                                                                 const int* __restrict__ tile_planes,
-                                                                 float2* __restrict__ A, float scale,
-                                                                 const float2* __restrict__ twM) {
-  using C = ColCfg<M>;
-  constexpr int V = C::V, G = C::G, TW = C::TW;
-  __shared__ float2 lds[TW * lds_len(M)];
-  const int col = threadIdx.x % TW;
-  const int j = threadIdx.x / TW;
-  const int tile = blockIdx.x / batch;
-  const int b = blockIdx.x % batch;
-  const int c = tile * TW + col;
-  const bool in_plane = c < H;
-  float2* my = lds + col * lds_len(M);
-  float2 acc[V];
-#pragma unroll
-  for (int s = 0; s < V; ++s) acc[s] = make_float2(0.f, 0.f);
-
-  const int p0 = tile_ptr[tile], p1 = tile_ptr[tile + 1];
-  for (int q = p0; q < p1; ++q) {
-    const int i = tile_planes[q];
-    const int lo = win.lo[i], w = win.w[i];
-    const bool valid = in_plane && c >= lo && c < lo + w;
-    const float2* zb = Z + (long long)b * img_stride + win.off[i] + (c - lo);
-    float2 u[V];
-#pragma unroll
-    for (int s = 0; s < V; ++s) u[s] = valid ? zb[(long long)(j + G * s) * w] : make_float2(0.f, 0.f);
-    fft_group<M, V, false>(u, j, my, twM, 1);
-    const float* pb = psi + (long long)i * M * H + c;
-#pragma unroll
-    for (int s = 0; s < V; ++s) {
-      const float ps = valid ? pb[(long long)(j + G * s) * H] : 0.f;
-      acc[s].x += ps * u[s].x;
-      acc[s].y += ps * u[s].y;
+      for (int s = 0; s < V; ++s) base[j + G * s] = v[s];
     }
   }
+}
+
+struct FwdLineJob {
+  const float2* F;          // [nimg][H][M]
+  const float* psi;         // [eta][H][M]
+  const int2* lines;        // (spectrum, column) of the unit's lines
+  int nlines, nimg, H;
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+
+// Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image).
+template <int M>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.nlines * job.nimg;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int img = qq / job.nlines;           // lines of one image are ordered by column,
+    const int2 ln = job.lines[qq % job.nlines];  // so neighbouring lines share F[c]
+    const int i = ln.x, c = ln.y;
+    const float2* fb = job.F + ((long long)img * job.H + c) * M;
+    const float* pb = job.psi + ((long long)i * job.H + c) * M;
+    float2 v[V];
 #pragma unroll
-  for (int s = 0; s < V; ++s) acc[s] = cscale(acc[s], scale);
-  fft_group<M, V, true>(acc, j, my, twM, 1);
-  if (!in_plane) return;
-  float2* ab = A + (long long)b * M * H + c;
+    for (int s = 0; s < V; ++s) v[s] = cscale(fb[j + G * s], pb[j + G * s] * job.scale);
+    fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
+    if (ok) {
+      float2* yb = job.Y + img * job.y_img_stride + (job.win.off[i] - job.y_off_base) +
+                   (long long)(c - job.win.lo[i]) * M;
 #pragma unroll
-  for (int s = 0; s < V; ++s) ab[(long long)(j + G * s) * H] = acc[s];
+      for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
+    }
+  }
+}
+
+struct AdjLineJob {
+  const float2* Z;
+  long long z_img_stride, z_off_base;
+  Windows win;
+  const float* psi;
+  const int* col_ptr;       // CSR over columns -> spectra of this plane group
+  const int* col_planes;
+  int H, nimg, nparts;
+  int accumulate;           // add to the existing partial sums
+  float2* out;              // FUSED: A [nimg][H][M]; else partial sums [nparts][nimg][H][M]
+  float scale;
+  const float2* twM;
+};
+
+// Line (img, c, part): sum_i Psi_i[c] * fft_col(Z_i[c - lo_i]) over the spectra
+// of column c (part p takes every nparts-th of them); FUSED: scale, inverse
+// FFT and store A[c].
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  float2* my = lds + g * C::STRIDE;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.H * job.nimg * job.nparts;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int part = qq % job.nparts;
+    const int rest = qq / job.nparts;
+    const int img = rest % job.nimg;
+    const int c = rest / job.nimg;
+    float2 acc[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc[s] = make_float2(0.f, 0.f);
+    const float2* zimg = job.Z + img * job.z_img_stride - job.z_off_base;
+    const int q1 = ok ? job.col_ptr[c + 1] : 0;
+    int t = job.col_ptr[c] + part;
+    // software pipeline: the next spectrum's lines are in flight while the
+    // current one is transformed
+    float2 zn[V];
+    float pn[V];
+    if (t < q1) {
+      const int i = job.col_planes[t];
+      const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * M;
+      const float* pb = job.psi + ((long long)i * job.H + c) * M;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        zn[s] = zb[j + G * s];
+        pn[s] = pb[j + G * s];
+      }
+    }
+    for (; t < q1; t += job.nparts) {
+      float2 v[V];
+      float ps[V];
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        v[s] = zn[s];
+        ps[s] = pn[s];
+      }
+      const int tn = t + job.nparts;
+      if (tn < q1) {
+        const int i = job.col_planes[tn];
+        const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * M;
+        const float* pb = job.psi + ((long long)i * job.H + c) * M;
+#pragma unroll
+        for (int s = 0; s < V; ++s) {
+          zn[s] = zb[j + G * s];
+          pn[s] = pb[j + G * s];
+        }
+      }
+      fft_group<M, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        acc[s].x += ps[s] * v[s].x;
+        acc[s].y += ps[s] * v[s].y;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc[s] = cscale(acc[s], job.scale);
+    if constexpr (FUSED) {
+      fft_group<M, V, true, C::SYNC>(acc, j, my, tw);
+      if (ok) {
+        float2* ab = job.out + ((long long)img * job.H + c) * M;
+#pragma unroll
+        for (int s = 0; s < V; ++s) ab[j + G * s] = acc[s];
+      }
+    } else if (ok) {
+      float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * M;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        float2 val = acc[s];
+        if (job.accumulate) val = cadd(val, pb[j + G * s]);
+        pb[j + G * s] = val;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------ dispatch
 
-// Row kernels take the complex length L = N/2, column kernels the length M.
+// Row kernels take the complex length L = N/2, line kernels the length M.
 #define FFST_ROW_CASES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048)
 #define FFST_COL_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+int g_num_cus = 0;
+
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      g_num_cus = prop.multiProcessorCount;
+    if (g_num_cus <= 0) g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+// Persistent grids: enough blocks for the work, at most `per_cu` per CU.
+int grid_for(long long units, int threads) {
+  const int per_cu = threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8);
+  const long long cap = (long long)num_cus() * per_cu;
+  return (int)(units < cap ? (units > 0 ? units : 1) : cap);
+}
 
 }  // namespace
 
@@ -269,25 +481,37 @@ bool supported_length(int L) {
   }
 }
 
-int col_tile_width(int M) {
-  switch (M) {
-#define CASE(n) case n: return ColCfg<n>::TW;
-    FFST_COL_CASES(CASE)
-#undef CASE
-    default: return 0;
-  }
+static RowJob make_row_job(const RowArgs& a, int rb_max) {
+  RowJob j;
+  j.x = a.x;
+  j.z = a.z;
+  j.x_img_stride = a.x_img_stride;
+  j.z_img_stride = a.z_img_stride;
+  j.z_off_base = a.z_off_base;
+  j.nimg = a.nimg;
+  j.nplanes = a.nplanes;
+  j.plane0 = a.plane0;
+  j.M = a.M;
+  j.rb = a.M < rb_max ? a.M : rb_max;
+  j.inv_nplanes = 1.0f / (float)a.nplanes;
+  j.win = a.win;
+  j.twN = a.twN;
+  return j;
 }
 
-hipError_t launch_r2c_rows(int N, const float* x, long long nrows, int M, int planes, float2* out,
-                           long long img_stride, Windows win, const float2* twN, hipStream_t s) {
-  const int L = N / 2;
-  switch (L) {
-#define CASE(n)                                                                                      \
-  case n: {                                                                                          \
-    const long long blocks = (nrows + RowCfg<n>::RB - 1) / RowCfg<n>::RB;                            \
-    hipLaunchKernelGGL(k_r2c_rows<n>, dim3((unsigned)blocks), dim3(kRowBlock), 0, s, x, nrows, M,   \
-                       planes, out, img_stride, win, twN);                                          \
-    return hipGetLastError();                                                                        \
+hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s) {
+  if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  switch (a.N / 2) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const RowJob job = make_row_job(a, RowCfg<n>::RB);                                            \
+    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
+    const dim3 grid(grid_for(units, RowCfg<n>::THREADS)), block(RowCfg<n>::THREADS);             \
+    if (job.rb < RowCfg<n>::RB)                                                                   \
+      hipLaunchKernelGGL((k_r2c_rows<n, true>), grid, block, 0, s, job);                              \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_r2c_rows<n, false>), grid, block, 0, s, job);                             \
+    return hipGetLastError();                                                                     \
   }
     FFST_ROW_CASES(CASE)
 #undef CASE
@@ -295,16 +519,19 @@ hipError_t launch_r2c_rows(int N, const float* x, long long nrows, int M, int pl
   }
 }
 
-hipError_t launch_c2r_rows(int N, const float2* in, long long img_stride, Windows win, long long nrows,
-                           int M, int planes, float* y, float scale, const float2* twN, hipStream_t s) {
-  const int L = N / 2;
-  switch (L) {
-#define CASE(n)                                                                                      \
-  case n: {                                                                                          \
-    const long long blocks = (nrows + RowCfg<n>::RB - 1) / RowCfg<n>::RB;                            \
-    hipLaunchKernelGGL(k_c2r_rows<n>, dim3((unsigned)blocks), dim3(kRowBlock), 0, s, in, img_stride,\
-                       win, nrows, M, planes, y, scale, twN);                                       \
-    return hipGetLastError();                                                                        \
+hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s) {
+  if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  switch (a.N / 2) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const RowJob job = make_row_job(a, RowCfg<n>::RB);                                            \
+    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
+    const dim3 grid(grid_for(units, RowCfg<n>::THREADS)), block(RowCfg<n>::THREADS);             \
+    if (job.rb < RowCfg<n>::RB)                                                                   \
+      hipLaunchKernelGGL((k_c2r_rows<n, true>), grid, block, 0, s, job);                              \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_c2r_rows<n, false>), grid, block, 0, s, job);                             \
+    return hipGetLastError();                                                                     \
   }
     FFST_ROW_CASES(CASE)
 #undef CASE
@@ -312,14 +539,21 @@ hipError_t launch_c2r_rows(int N, const float2* in, long long img_stride, Window
   }
 }
 
-hipError_t launch_fft_cols_image(int M, int N, float2* F, int batch, const float2* twM, hipStream_t s) {
-  const int H = N / 2 + 1;
+hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const float2* parts, int nparts,
+                           long long part_stride, const float2* twM, hipStream_t s) {
+  if (nlines == 0) return hipSuccess;
   switch (M) {
-#define CASE(n)                                                                                      \
-  case n: {                                                                                          \
-    dim3 grid((unsigned)((H + ColCfg<n>::TW - 1) / ColCfg<n>::TW), (unsigned)batch);                \
-    hipLaunchKernelGGL(k_fft_cols_image<n>, grid, dim3(ColCfg<n>::THREADS), 0, s, F, H, twM);        \
-    return hipGetLastError();                                                                        \
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (nlines + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                     \
+    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
+    if (inverse)                                                                                  \
+      hipLaunchKernelGGL((k_line_fft<n, true>), grid, block, 0, s, F, nlines, parts, nparts,      \
+                         part_stride, twM);                                                       \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_line_fft<n, false>), grid, block, 0, s, F, nlines, parts, nparts,     \
+                         part_stride, twM);                                                       \
+    return hipGetLastError();                                                                     \
   }
     FFST_COL_CASES(CASE)
 #undef CASE
@@ -327,17 +561,18 @@ hipError_t launch_fft_cols_image(int M, int N, float2* F, int batch, const float
   }
 }
 
-hipError_t launch_fwd_cols(int M, int N, const float2* F, const float* psi, int batch, const int2* items,
-                           int nitems, Windows win, long long img_stride, float2* Y, float scale,
-                           const float2* twM, hipStream_t s) {
-  const int H = N / 2 + 1;
-  switch (M) {
-#define CASE(n)                                                                                      \
-  case n: {                                                                                          \
-    dim3 grid((unsigned)((long long)nitems * batch));                                                \
-    hipLaunchKernelGGL(k_fwd_cols<n>, grid, dim3(ColCfg<n>::THREADS), 0, s, F, psi, H, batch, items, \
-                       win, img_stride, Y, scale, twM);                                              \
-    return hipGetLastError();                                                                        \
+hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
+  FwdLineJob job{a.F, a.psi, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.win, a.y_img_stride, a.y_off_base,
+                 a.Y, a.scale, a.twM};
+  if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.nlines * job.nimg;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    hipLaunchKernelGGL(k_fwd_lines<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),                \
+                       dim3(LineCfg<n>::THREADS), 0, s, job);                                     \
+    return hipGetLastError();                                                                     \
   }
     FFST_COL_CASES(CASE)
 #undef CASE
@@ -345,17 +580,21 @@ hipError_t launch_fwd_cols(int M, int N, const float2* F, const float* psi, int 
   }
 }
 
-hipError_t launch_adj_cols(int M, int N, const float2* Z, long long img_stride, Windows win,
-                           const float* psi, int batch, const int* tile_ptr, const int* tile_planes,
-                           int ntiles, float2* A, float scale, const float2* twM, hipStream_t s) {
-  const int H = N / 2 + 1;
-  switch (M) {
-#define CASE(n)                                                                                      \
-  case n: {                                                                                          \
-    dim3 grid((unsigned)((long long)ntiles * batch));                                                \
-    hipLaunchKernelGGL(k_adj_cols<n>, grid, dim3(ColCfg<n>::THREADS), 0, s, Z, img_stride, win, psi, \
-                       H, batch, tile_ptr, tile_planes, A, scale, twM);                              \
-    return hipGetLastError();                                                                        \
+hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
+  AdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psi, a.col_ptr, a.col_planes, a.N / 2 + 1,
+                 a.nimg, a.nparts, a.accumulate, a.out, a.scale, a.twM};
+  if (job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.H * job.nimg * job.nparts;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
+    if (a.fused)                                                                                  \
+      hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                         \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                        \
+    return hipGetLastError();                                                                     \
   }
     FFST_COL_CASES(CASE)
 #undef CASE
