@@ -1,0 +1,64 @@
+"""Differentiable shearlet transform on the GPU.
+
+The forward transform is linear, c = SH f, so its vector-Jacobian product is
+the adjoint: d<g, SH f>/df = SH* g (Sec. 3.2-3.3: SH* is the inverse of the
+Parseval frame, eq. inverseShearletTransform). `ShearletTransform.backward`
+therefore calls the library's adjoint kernels; `ShearletAdjoint` is the
+mirror image (its backward is the forward transform).
+
+`l1_denoise` runs plain (sub)gradient descent on
+    L(x) = 1/2 ||x - y||^2 + lam ||SH x||_1
+with the gradient from autograd, i.e. from the adjoint kernels.
+"""
+
+import torch
+
+
+class ShearletTransform(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, plan):
+        ctx.plan = plan
+        return plan.forward(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        return ctx.plan.adjoint(grad_c.contiguous()), None
+
+
+class ShearletAdjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, c, plan):
+        ctx.plan = plan
+        return plan.adjoint(c.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        return ctx.plan.forward(grad_f.contiguous()), None
+
+
+def shearlet_transform(x, plan):
+    """SH x with gradients through the adjoint kernels."""
+    return ShearletTransform.apply(x, plan)
+
+
+def shearlet_adjoint(c, plan):
+    """SH* c with gradients through the forward kernels."""
+    return ShearletAdjoint.apply(c, plan)
+
+
+def l1_loss(x, y, plan, lam):
+    """1/2 ||x - y||^2 + lam ||SH x||_1, summed over the batch."""
+    return 0.5 * ((x - y) ** 2).sum() + lam * shearlet_transform(x, plan).abs().sum()
+
+
+def l1_denoise(y, plan, lam=0.05, steps=200, lr=0.5, x0=None):
+    """Gradient descent on l1_loss from x0 (default y); returns (x, losses)."""
+    x = (y.clone() if x0 is None else x0.clone()).requires_grad_(True)
+    losses = []
+    for _ in range(steps):
+        loss = l1_loss(x, y, plan, lam)
+        (g,) = torch.autograd.grad(loss, x)
+        with torch.no_grad():
+            x -= lr * g
+        losses.append(loss.detach())
+    return x.detach(), torch.stack(losses)
