@@ -15,6 +15,7 @@ using namespace ffst;
 
 struct ffst_plan {
   int M = 0, N = 0, J = 0, eta = 0, H = 0;
+  int pitch = 0;                // complex elements between column lines of the complex buffers
   int device = -1;
   ffst_options opt{};
   double delta = 0.0;
@@ -73,14 +74,26 @@ struct ProfRec {
 };
 unsigned g_mask = 0;
 std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;  // events reused across timed launches
 double g_total_ms[KID_COUNT] = {};
 long long g_count[KID_COUNT] = {};
+
+hipEvent_t pooled_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
 
 template <class Fn>
 hipError_t timed(int id, hipStream_t s, Fn&& fn) {
   if (!((g_mask >> id) & 1u)) return fn();
-  ProfRec r{id, nullptr, nullptr};
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return fn();
+  ProfRec r{id, pooled_event(), pooled_event()};
+  if (!r.a || !r.b) return fn();
   (void)hipEventRecord(r.a, s);
   hipError_t e = fn();
   (void)hipEventRecord(r.b, s);
@@ -95,8 +108,8 @@ void drain_profile() {
       g_total_ms[r.id] += ms;
       g_count[r.id] += 1;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
   }
   g_recs.clear();
 }
@@ -177,7 +190,7 @@ Schedule schedule(const ffst_plan* p, int batch) {
   const int ngroups = (int)p->groups.size() - 1;
   long long max_group = 0;
   for (int g = 0; g < ngroups; ++g)
-    max_group = std::max(max_group, p->off[p->groups[g + 1] - 1] + (long long)p->M * p->w[p->groups[g + 1] - 1] -
+    max_group = std::max(max_group, p->off[p->groups[g + 1] - 1] + (long long)p->pitch * p->w[p->groups[g + 1] - 1] -
                                         p->off[p->groups[g]]);
   if (ngroups == 1 && p->zimg > 0)
     sc.chunk_imgs = (int)std::max(1LL, std::min<long long>(batch, p->chunk_elems / std::max(1LL, p->zimg)));
@@ -190,10 +203,11 @@ Schedule schedule(const ffst_plan* p, int batch) {
   const long long units = (long long)p->H * sc.chunk_imgs;
   const long long want = 8LL * 256;
   sc.nparts = (int)std::min<long long>(8, std::max<long long>(1, (want + units - 1) / units));
+  if (const char* e = std::getenv("FFST_NPARTS")) sc.nparts = std::max(1, std::min(8, std::atoi(e)));
   sc.fused = (ngroups == 1 && sc.nparts == 1);
-  sc.fa_bytes = align256((size_t)batch * p->M * p->H * sizeof(float2));
+  sc.fa_bytes = align256((size_t)batch * p->pitch * p->H * sizeof(float2));
   sc.yz_bytes = align256((size_t)sc.chunk_imgs * (size_t)max_group * sizeof(float2));
-  sc.part_bytes = sc.fused ? 0 : align256((size_t)sc.nparts * sc.chunk_imgs * p->M * p->H * sizeof(float2));
+  sc.part_bytes = sc.fused ? 0 : align256((size_t)sc.nparts * sc.chunk_imgs * p->pitch * p->H * sizeof(float2));
   return sc;
 }
 
@@ -264,6 +278,10 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   p->N = N;
   p->J = J;
   p->H = N / 2 + 1;
+  // Column lines of the complex buffers are padded by 128 bytes so that the
+  // 16-row segments of neighbouring columns do not all share the address
+  // bits above 4 KB.
+  p->pitch = M >= 64 ? M + 16 : M;
   p->eta = (1 << (J + 2)) - 3;
   p->opt = o;
   p->magic = kMagic;
@@ -326,7 +344,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       p->w[i] = hi[i] - p->lo[i] + 1;
     }
     p->off[i] = acc;
-    acc += (long long)M * p->w[i];
+    acc += (long long)p->pitch * p->w[i];
     p->line_ptr[i] = (int)lines.size();
     for (int c = p->lo[i]; c < p->lo[i] + p->w[i]; ++c) lines.push_back(make_int2(i, c));
   }
@@ -341,7 +359,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   p->groups = {0};
   long long gsize = 0;
   for (int i = 0; i < p->eta; ++i) {
-    const long long sz = (long long)M * p->w[i];
+    const long long sz = (long long)p->pitch * p->w[i];
     if (gsize > 0 && gsize + sz > p->chunk_elems) {
       p->groups.push_back(i);
       gsize = 0;
@@ -424,16 +442,16 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   const Schedule sc = schedule(p, batch);
   float2* F = static_cast<float2*>(ws);
   float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
-  const long long MH = (long long)p->M * p->H;
+  const long long MH = (long long)p->pitch * p->H;   // one image of F / A
   const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
 
   // F = fft2(f) on the half plane, column-contiguous
-  RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, image_window(p), p->twN};
+  RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
   hipError_t e = timed(KID_R2C_IMAGE, s, [&] { return launch_r2c_rows(ra, s); });
   if (e == hipSuccess)
     e = timed(KID_FFT_COLS_IMAGE, s,
-              [&] { return launch_line_fft(p->M, F, batch * p->H, false, nullptr, 0, 0, p->twM, s); });
+              [&] { return launch_line_fft(p->M, F, batch * p->H, p->pitch, false, nullptr, 0, 0, p->twM, s); });
 
   const int ngroups = (int)p->groups.size() - 1;
   for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
@@ -443,12 +461,12 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
       FwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psi, p->d_lines + p->line_ptr[p0],
-                     p->line_ptr[p1] - p->line_ptr[p0], nimg, plane_windows(p), unit_stride, base, Y, scale,
-                     p->twM};
+                     p->line_ptr[p1] - p->line_ptr[p0], nimg, p->pitch, plane_windows(p), unit_stride, base, Y,
+                     scale, p->twM};
       e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_lines(fa, s); });
       if (e != hipSuccess) break;
       RowArgs rc{coeffs + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
-                 p->M, p->N, plane_windows(p), p->twN};
+                 p->M, p->N, p->pitch, plane_windows(p), p->twN};
       e = timed(KID_C2R_PLANES, s, [&] { return launch_c2r_rows(rc, s); });
     }
   }
@@ -466,7 +484,7 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
   float2* A = static_cast<float2*>(ws);
   float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
   float2* P = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes + sc.yz_bytes);
-  const long long MH = (long long)p->M * p->H;
+  const long long MH = (long long)p->pitch * p->H;   // one image of F / A
   const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
   const int ngroups = (int)p->groups.size() - 1;
@@ -478,22 +496,22 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
       RowArgs rr{const_cast<float*>(coeffs) + img0 * p->eta * MN, Z, p->eta * MN, unit_stride, base, nimg,
-                 p1 - p0, p0, p->M, p->N, plane_windows(p), p->twN};
+                 p1 - p0, p0, p->M, p->N, p->pitch, plane_windows(p), p->twN};
       e = timed(KID_R2C_PLANES, s, [&] { return launch_r2c_rows(rr, s); });
       if (e != hipSuccess) break;
       AdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psi,
                      p->d_col_ptr + g * (p->H + 1), p->d_col_planes, nimg, sc.nparts, g > 0 ? 1 : 0,
-                     sc.fused ? 1 : 0, sc.fused ? A + img0 * MH : P, scale, p->twM};
+                     sc.fused ? 1 : 0, p->pitch, sc.fused ? A + img0 * MH : P, scale, p->twM};
       e = timed(KID_ADJ_COLS, s, [&] { return launch_adj_lines(aa, s); });
     }
     if (e == hipSuccess && !sc.fused)
       e = timed(KID_IFFT_COLS_IMAGE, s, [&] {
-        return launch_line_fft(p->M, A + img0 * MH, nimg * p->H, true, P, sc.nparts, (long long)nimg * MH,
-                               p->twM, s);
+        return launch_line_fft(p->M, A + img0 * MH, nimg * p->H, p->pitch, true, P, sc.nparts,
+                               (long long)nimg * MH, p->twM, s);
       });
   }
   if (e == hipSuccess) {
-    RowArgs rc{f, A, MN, MH, 0, batch, 1, 0, p->M, p->N, image_window(p), p->twN};
+    RowArgs rc{f, A, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
     e = timed(KID_C2R_IMAGE, s, [&] { return launch_c2r_rows(rc, s); });
   }
   return launched(e, "ffst_adjoint");

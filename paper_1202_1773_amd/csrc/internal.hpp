@@ -49,13 +49,14 @@ hipError_t launch_expand(const float* psi, int M, int N, int eta, int cols, floa
 // img < nimg, plane0 <= plane < plane0 + nplanes, r < M; real row
 // (img, plane, r) starts at x + img*x_img_stride + (plane*M + r)*N. The
 // complex side is column-contiguous: column c of (img, plane) holds M values
-// at z + img*z_img_stride + (win.off[plane] - z_off_base) + (c - lo)*M, for
+// at z + img*z_img_stride + (win.off[plane] - z_off_base) + (c - lo)*zp, for
 // the half-plane columns c in [lo, lo + w) of the plane's window.
 struct RowArgs {
   float* x;
   float2* z;
   long long x_img_stride, z_img_stride, z_off_base;
   int nimg, nplanes, plane0, M, N;
+  int zp;                   // complex elements between consecutive columns of z
   Windows win;
   const float2* twN;
 };
@@ -64,7 +65,7 @@ hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s);
 
 // In-place FFT of nlines contiguous lines of length M; the inverse may first
 // replace each line by the sum of the same line in `nparts` partial arrays.
-hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const float2* parts, int nparts,
+hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse, const float2* parts, int nparts,
                            long long part_stride, const float2* twM, hipStream_t s);
 
 struct FwdLineArgs {
@@ -73,6 +74,7 @@ struct FwdLineArgs {
   const float* psi;         // [eta][N/2+1][M]
   const int2* lines;        // (spectrum, column)
   int nlines, nimg;
+  int pitch;                // complex elements between column lines of F and Y
   Windows win;
   long long y_img_stride, y_off_base;
   float2* Y;
@@ -90,6 +92,7 @@ struct AdjLineArgs {
   const int* col_ptr;
   const int* col_planes;
   int nimg, nparts, accumulate, fused;
+  int pitch;                // complex elements between column lines of Z, A and partial sums
   float2* out;
   float scale;
   const float2* twM;

@@ -38,6 +38,9 @@ namespace ffst {
 namespace {
 
 __host__ __device__ constexpr int line_values(int L) { return L >= 16 ? 16 : L; }
+// Column lines: 8 values per lane up to length 1024 (8*8*8 needs the same
+// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above.
+__host__ __device__ constexpr int col_values(int L) { return L > 1024 ? 16 : (L >= 8 ? 8 : L); }
 // LDS stride per line/row: congruent to 17 mod 32, so that 16 lanes reading
 // the same column of 16 rows, and 16 lanes reading 16 consecutive values of
 // one row, both touch distinct banks.
@@ -57,7 +60,7 @@ struct RowCfg {
 // Contiguous lines of length L (the column direction, L = M).
 template <int L>
 struct LineCfg {
-  static constexpr int V = line_values(L);
+  static constexpr int V = col_values(L);
   static constexpr int G = L / V;
   static constexpr int SYNC = G <= 64 ? kWave : kBlock;
   static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
@@ -70,9 +73,10 @@ struct LineCfg {
 struct RowJob {
   float* x;                 // real rows: row (img, plane, r) at x + img*x_img_stride + (plane*M + r)*N
   float2* z;                // compact columns: (img, plane, c, r) at z + img*z_img_stride +
-                            //   (win.off[plane] - z_off_base) + (c - lo)*M + r
+                            //   (win.off[plane] - z_off_base) + (c - lo)*zp + r
   long long x_img_stride, z_img_stride, z_off_base;
   int nimg, nplanes, plane0, M, rb;   // rb = rows per block (divides M)
+  int zp;                   // complex elements between consecutive columns of z (>= M)
   float inv_nplanes;
   Windows win;
   const float2* twN;        // exp(-2 pi i m / N), m < N
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
       const float2 zm = conjf2(zr[lpad<V>((L - c) & (L - 1))]);
       const float2 a = cadd(zc, zm);
       const float2 b = cmul(job.twN[c], csub(zc, zm));
-      out[(long long)(c - lo) * job.M] = make_float2(0.5f * (a.x + b.y), 0.5f * (a.y - b.x));
+      out[(long long)(c - lo) * job.zp] = make_float2(0.5f * (a.x + b.y), 0.5f * (a.y - b.x));
     }
     __syncthreads();
   }
@@ -186,7 +190,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
 #pragma unroll
     for (int m = 0; m < NLD; ++m) {
       const int k = tc + step * m;
-      dst[m] = (k <= L && (unsigned)(k - lo) < (unsigned)w) ? in[(long long)(k - lo) * job.M] : make_float2(0.f, 0.f);
+      dst[m] = (k <= L && (unsigned)(k - lo) < (unsigned)w) ? in[(long long)(k - lo) * job.zp] : make_float2(0.f, 0.f);
     }
   };
 
@@ -197,7 +201,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
       const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
       const float2* in = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
       for (int k = tc; k <= L; k += NT / rb)
-        zr[lpad<V>(k)] = (unsigned)(k - lo) < (unsigned)w ? in[(long long)(k - lo) * job.M] : make_float2(0.f, 0.f);
+        zr[lpad<V>(k)] = (unsigned)(k - lo) < (unsigned)w ? in[(long long)(k - lo) * job.zp] : make_float2(0.f, 0.f);
       __syncthreads();
       float2 v[V];
 #pragma unroll
@@ -260,7 +264,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
 // each line is first replaced by the sum of the same line of `nparts`
 // partial arrays (parts + p * part_stride), added in order p = 0, 1, ...
 template <int M, bool INV>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines,
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines, int pitch,
                                                                   const float2* __restrict__ parts, int nparts,
                                                                   long long part_stride,
                                                                   const float2* __restrict__ twM) {
@@ -274,16 +278,24 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __rest
   for (int u = blockIdx.x; u * C::LPB < nlines; u += gridDim.x) {
     const int line = u * C::LPB + g;
     const bool ok = line < nlines;
-    float2* base = F + (long long)(ok ? line : 0) * M;
+    float2* base = F + (long long)(ok ? line : 0) * pitch;
     float2 v[V];
     if (nparts > 0) {
 #pragma unroll
       for (int s = 0; s < V; ++s) v[s] = make_float2(0.f, 0.f);
-      for (int p = 0; p < nparts; ++p) {
-        const float2* pb = parts + p * part_stride + (long long)(ok ? line : 0) * M;
+      // up to 8 partial arrays, all loads issued before the (fixed-order) sums
+      constexpr int MAXP = 8;
+      float2 t[MAXP][V];
 #pragma unroll
-        for (int s = 0; s < V; ++s) v[s] = cadd(v[s], pb[j + G * s]);
+      for (int p = 0; p < MAXP; ++p) {
+        const float2* pb = parts + p * part_stride + (long long)(ok ? line : 0) * pitch;
+#pragma unroll
+        for (int s = 0; s < V; ++s) t[p][s] = p < nparts ? pb[j + G * s] : make_float2(0.f, 0.f);
       }
+#pragma unroll
+      for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+        for (int s = 0; s < V; ++s) v[s] = cadd(v[s], t[p][s]);
     } else {
 #pragma unroll
       for (int s = 0; s < V; ++s) v[s] = base[j + G * s];
@@ -301,6 +313,7 @@ struct FwdLineJob {
   const float* psi;         // [eta][H][M]
   const int2* lines;        // (spectrum, column) of the unit's lines
   int nlines, nimg, H;
+  int pitch;                // complex elements between column lines of F and Y
   Windows win;
   long long y_img_stride, y_off_base;
   float2* Y;
@@ -319,22 +332,40 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob jo
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.nlines * job.nimg;
-  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
+  // software pipeline: the next unit's F and Psi lines are loaded while the
+  // current line is transformed
+  float2 fn[V];
+  float pn[V];
+  auto load_unit = [&](int u) {
+    const int q = u * C::LPB + g;
+    const int qq = q < total ? q : 0;
+    const int img = qq / job.nlines;
+    const int2 ln = job.lines[qq % job.nlines];
+    const float2* fb = job.F + ((long long)img * job.H + ln.y) * job.pitch;
+    const float* pb = job.psi + ((long long)ln.x * job.H + ln.y) * M;
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      fn[s] = fb[j + G * s];
+      pn[s] = pb[j + G * s];
+    }
+  };
+  int u = blockIdx.x;
+  if (u * C::LPB < total) load_unit(u);
+  for (; u * C::LPB < total; u += gridDim.x) {
     const int q = u * C::LPB + g;
     const bool ok = q < total;
     const int qq = ok ? q : 0;
-    const int img = qq / job.nlines;           // lines of one image are ordered by column,
+    const int img = qq / job.nlines;          // lines of one image are ordered by column,
     const int2 ln = job.lines[qq % job.nlines];  // so neighbouring lines share F[c]
     const int i = ln.x, c = ln.y;
-    const float2* fb = job.F + ((long long)img * job.H + c) * M;
-    const float* pb = job.psi + ((long long)i * job.H + c) * M;
     float2 v[V];
 #pragma unroll
-    for (int s = 0; s < V; ++s) v[s] = cscale(fb[j + G * s], pb[j + G * s] * job.scale);
+    for (int s = 0; s < V; ++s) v[s] = cscale(fn[s], pn[s] * job.scale);
+    if ((u + (int)gridDim.x) * C::LPB < total) load_unit(u + gridDim.x);
     fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
     if (ok) {
       float2* yb = job.Y + img * job.y_img_stride + (job.win.off[i] - job.y_off_base) +
-                   (long long)(c - job.win.lo[i]) * M;
+                   (long long)(c - job.win.lo[i]) * job.pitch;
 #pragma unroll
       for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
     }
@@ -349,6 +380,7 @@ struct AdjLineJob {
   const int* col_ptr;       // CSR over columns -> spectra of this plane group
   const int* col_planes;
   int H, nimg, nparts;
+  int pitch;                // complex elements between column lines of Z, A and the partial sums
   int accumulate;           // add to the existing partial sums
   float2* out;              // FUSED: A [nimg][H][M]; else partial sums [nparts][nimg][H][M]
   float scale;
@@ -359,7 +391,7 @@ struct AdjLineJob {
 // of column c (part p takes every nparts-th of them); FUSED: scale, inverse
 // FFT and store A[c].
 template <int M, bool FUSED>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob job) {
+__device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
@@ -389,7 +421,7 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob jo
     float pn[V];
     if (t < q1) {
       const int i = job.col_planes[t];
-      const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * M;
+      const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
       const float* pb = job.psi + ((long long)i * job.H + c) * M;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
@@ -408,7 +440,7 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob jo
       const int tn = t + job.nparts;
       if (tn < q1) {
         const int i = job.col_planes[tn];
-        const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * M;
+        const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
         const float* pb = job.psi + ((long long)i * job.H + c) * M;
 #pragma unroll
         for (int s = 0; s < V; ++s) {
@@ -428,12 +460,12 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob jo
     if constexpr (FUSED) {
       fft_group<M, V, true, C::SYNC>(acc, j, my, tw);
       if (ok) {
-        float2* ab = job.out + ((long long)img * job.H + c) * M;
+        float2* ab = job.out + ((long long)img * job.H + c) * job.pitch;
 #pragma unroll
         for (int s = 0; s < V; ++s) ab[j + G * s] = acc[s];
       }
     } else if (ok) {
-      float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * M;
+      float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * job.pitch;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         float2 val = acc[s];
@@ -442,6 +474,19 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob jo
       }
     }
   }
+}
+
+// Up to M = 1024 the body fits 128 registers (4 waves per SIMD) with a few
+// spills; larger lengths keep the compiler's own allocation.
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k_adj_lines(AdjLineJob job) {
+  adj_lines_body<M, FUSED>(job);
+}
+
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_wide(AdjLineJob job) {
+  adj_lines_body<M, FUSED>(job);
 }
 
 // ------------------------------------------------------------ dispatch
@@ -493,6 +538,7 @@ static RowJob make_row_job(const RowArgs& a, int rb_max) {
   j.plane0 = a.plane0;
   j.M = a.M;
   j.rb = a.M < rb_max ? a.M : rb_max;
+  j.zp = a.zp;
   j.inv_nplanes = 1.0f / (float)a.nplanes;
   j.win = a.win;
   j.twN = a.twN;
@@ -539,7 +585,7 @@ hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const float2* parts, int nparts,
+hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse, const float2* parts, int nparts,
                            long long part_stride, const float2* twM, hipStream_t s) {
   if (nlines == 0) return hipSuccess;
   switch (M) {
@@ -548,10 +594,10 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const flo
     const long long units = (nlines + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                     \
     const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
     if (inverse)                                                                                  \
-      hipLaunchKernelGGL((k_line_fft<n, true>), grid, block, 0, s, F, nlines, parts, nparts,      \
+      hipLaunchKernelGGL((k_line_fft<n, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
                          part_stride, twM);                                                       \
     else                                                                                          \
-      hipLaunchKernelGGL((k_line_fft<n, false>), grid, block, 0, s, F, nlines, parts, nparts,     \
+      hipLaunchKernelGGL((k_line_fft<n, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
                          part_stride, twM);                                                       \
     return hipGetLastError();                                                                     \
   }
@@ -562,8 +608,8 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, bool inverse, const flo
 }
 
 hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
-  FwdLineJob job{a.F, a.psi, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.win, a.y_img_stride, a.y_off_base,
-                 a.Y, a.scale, a.twM};
+  FwdLineJob job{a.F, a.psi, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.pitch, a.win, a.y_img_stride,
+                 a.y_off_base, a.Y, a.scale, a.twM};
   if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
   const long long total = (long long)job.nlines * job.nimg;
   switch (a.M) {
@@ -582,7 +628,7 @@ hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
 
 hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
   AdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psi, a.col_ptr, a.col_planes, a.N / 2 + 1,
-                 a.nimg, a.nparts, a.accumulate, a.out, a.scale, a.twM};
+                 a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
   if (job.nimg == 0) return hipSuccess;
   const long long total = (long long)job.H * job.nimg * job.nparts;
   switch (a.M) {
@@ -590,10 +636,14 @@ hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
   case n: {                                                                                       \
     const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
     const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if (a.fused)                                                                                  \
+    if (n <= 1024 && a.fused)                                                                     \
       hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                         \
-    else                                                                                          \
+    else if (n <= 1024)                                                                           \
       hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                        \
+    else if (a.fused)                                                                             \
+      hipLaunchKernelGGL((k_adj_lines_wide<n, true>), grid, block, 0, s, job);                    \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_adj_lines_wide<n, false>), grid, block, 0, s, job);                   \
     return hipGetLastError();                                                                     \
   }
     FFST_COL_CASES(CASE)
