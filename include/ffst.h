@@ -74,12 +74,23 @@ typedef struct {
     int max_scale_min;   /* 0: X = 2^(2J-1) ('max', the default); 1: X = 2^(2J-2)
                             ('min'); option maxScale of Sec. 3.5.3 */
     int shearlet;        /* an ffst_shearlet value */
+    int complex_shearlets; /* 0: real shearlets (the default). 1: complex
+                            shearlets from one-sided spectra (Sec. 3.8.2):
+                            Psi+_i = sqrt(2) Psi_i on the side <omega, d_i> > 0
+                            of the line through 0 orthogonal to the centre
+                            direction d_i of shearlet i (d = (1, -k/2^j) for the
+                            h cone and the seam elements, (-k/2^j, 1) for the
+                            v cone), 0 on the other side, Psi_i unchanged on
+                            that line, on the low-pass, and at grid points
+                            whose DFT mirror lies on the same side. The
+                            coefficients are complex; such a plan is used with
+                            the *_complex transform calls only. */
 } ffst_options;
 
 /*
  * Create a plan for M x N images with J scales (J <= 0 selects the default
  * floor(1/2 log2 max(M, N)), Sec. 3.1) and generate its spectra on the
- * current HIP device (Sec. 3.5.1 "we precompute these spectra"). The
+ * current HIP device (once per plan, as Sec. 3.5.1 prescribes). The
  * spectra are evaluated in float64 and stored in float32. Synchronous: on
  * return the plan is ready. *out receives the plan, or NULL on failure.
  */
@@ -102,6 +113,8 @@ size_t ffst_workspace_size(const ffst_plan* plan, int batch);
  * evenness, Psi(r, c) = Psi(-r mod M, -c mod N)).
  */
 int ffst_get_spectra(const ffst_plan* plan, float* dst, int full_plane);
+/* For a complex-shearlet plan only full_plane = 1 is accepted; it writes the
+ * one-sided spectra Psi+_i [eta][M][N] (they are not even). */
 
 /*
  * Number of nonzero-column windows used to skip work: writes, for each
@@ -109,6 +122,9 @@ int ffst_get_spectra(const ffst_plan* plan, float* dst, int full_plane);
  * nonzero value (host arrays of eta ints each; -1/-1 for an all-zero plane).
  */
 int ffst_plan_windows(const ffst_plan* plan, int* first_col, int* last_col);
+/* For a complex-shearlet plan the windows are cyclic ranges of full-plane
+ * columns c in [0, N): the columns first_col, first_col + 1, ... (mod N) up to
+ * last_col, so last_col < first_col when the range wraps past N - 1. */
 
 /*
  * Forward transform of `batch` images: coeffs[b][i] = ifft2(Psi_i .* fft2(f[b])).
@@ -127,6 +143,27 @@ int ffst_adjoint(const ffst_plan* plan, const float* coeffs, float* f, int batch
 /* Inverse transform; the same computation as ffst_adjoint (Parseval frame). */
 int ffst_inverse(const ffst_plan* plan, const float* coeffs, float* f, int batch,
                  void* ws, void* stream);
+
+/*
+ * Complex shearlets (Sec. 3.8.2), on a plan created with complex_shearlets = 1.
+ * Coefficients are complex, stored as interleaved float pairs (re, im):
+ * coeffs [batch][eta][M][N][2], 8-byte aligned; the images stay real.
+ *
+ * Forward: coeffs[b][i] = ifft2(Psi+_i .* fft2(f[b])).
+ * Adjoint: f[b] = Re ifft2( sum_i Psi+_i .* fft2(coeffs[b][i]) ), the adjoint
+ *   of the forward map for the real inner product on the coefficients.
+ * Inverse: the same computation as the adjoint; for real images the one-
+ *   sided system is again a Parseval frame, since |Psi+_i(w)|^2 +
+ *   |Psi+_i(-w)|^2 = Psi_i(w)^2 + Psi_i(-w)^2 at every grid pair (w, -w).
+ * The real-shearlet calls reject complex plans and these calls reject real
+ * plans (FFST_EINVAL). Workspace, streams and errors as above.
+ */
+int ffst_forward_complex(const ffst_plan* plan, const float* f, float* coeffs, int batch,
+                         void* ws, void* stream);
+int ffst_adjoint_complex(const ffst_plan* plan, const float* coeffs, float* f, int batch,
+                         void* ws, void* stream);
+int ffst_inverse_complex(const ffst_plan* plan, const float* coeffs, float* f, int batch,
+                         void* ws, void* stream);
 
 /* Release a plan (NULL is ignored). Synchronises the device first. */
 void ffst_destroy(ffst_plan* plan);

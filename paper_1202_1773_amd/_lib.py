@@ -22,7 +22,8 @@ FFST_SHEARLET_MEYER_SMOOTH = 1
 EXPORTED = [
     "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
     "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
-    "ffst_inverse", "ffst_destroy", "ffst_last_error", "ffst_profile_enable",
+    "ffst_inverse", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
+    "ffst_destroy", "ffst_last_error", "ffst_profile_enable",
     "ffst_profile_read", "ffst_profile_reset", "ffst_num_kernels", "ffst_kernel_name",
 ]
 
@@ -34,7 +35,8 @@ class FfstError(RuntimeError):
 
 
 class ffst_options(ctypes.Structure):
-    _fields_ = [("max_scale_min", ctypes.c_int), ("shearlet", ctypes.c_int)]
+    _fields_ = [("max_scale_min", ctypes.c_int), ("shearlet", ctypes.c_int),
+                ("complex_shearlets", ctypes.c_int)]
 
 
 _lib = None
@@ -61,6 +63,9 @@ def load():
         "ffst_forward": (I, [P, P, P, I, P, P]),
         "ffst_adjoint": (I, [P, P, P, I, P, P]),
         "ffst_inverse": (I, [P, P, P, I, P, P]),
+        "ffst_forward_complex": (I, [P, P, P, I, P, P]),
+        "ffst_adjoint_complex": (I, [P, P, P, I, P, P]),
+        "ffst_inverse_complex": (I, [P, P, P, I, P, P]),
         "ffst_destroy": (None, [P]),
         "ffst_last_error": (ctypes.c_char_p, []),
         "ffst_profile_enable": (I, [ctypes.c_uint]),
@@ -85,11 +90,11 @@ def _check(status, where):
 
 # ---- thin wrappers with the C names ------------------------------------
 
-def ffst_spectra(M, N, J=0, max_scale="max", shearlet=FFST_SHEARLET_MEYER):
+def ffst_spectra(M, N, J=0, max_scale="max", shearlet=FFST_SHEARLET_MEYER, complex_shearlets=False):
     """Create a plan and generate its spectra; returns the opaque handle."""
     lib = load()
     out = ctypes.c_void_p()
-    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet))
+    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet), 1 if complex_shearlets else 0)
     _check(lib.ffst_spectra_ex(int(M), int(N), int(J), ctypes.byref(opt), ctypes.byref(out)), "ffst_spectra")
     return out.value
 
@@ -128,6 +133,21 @@ def ffst_adjoint(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
 def ffst_inverse(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
     _check(load().ffst_inverse(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
                                ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_inverse")
+
+
+def ffst_forward_complex(plan, f_ptr, c_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_forward_complex(plan, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), int(batch),
+                                       ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_forward_complex")
+
+
+def ffst_adjoint_complex(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_adjoint_complex(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
+                                       ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_adjoint_complex")
+
+
+def ffst_inverse_complex(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
+    _check(load().ffst_inverse_complex(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
+                                       ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_inverse_complex")
 
 
 def ffst_destroy(plan):

@@ -2,39 +2,58 @@
 
     python -m paper_1202_1773_amd.build          # or build() from Python
 
-Every call recompiles. Packed FP32 instructions are disabled for all device
-code (-Xclang -target-feature -Xclang -packed-fp32-ops).
+Every call recompiles: each source to an object file (in parallel), then one
+link. Packed FP32 instructions are disabled for all device code
+(-Xclang -target-feature -Xclang -packed-fp32-ops).
 """
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffst.so")
-SOURCES = ["spectra.hip", "transform.hip", "api.hip"]
+SOURCES = ["spectra.hip", "transform.hip", "complex.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+NOISE = "packed-fp32-ops"
+
+
+def _run(cmd):
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in res.stderr.splitlines() if NOISE not in l)
+    return res.returncode, err
 
 
 def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "packed-fp32-ops"
-    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if verbose and err.strip():
-        print(err, file=sys.stderr)
+    with tempfile.TemporaryDirectory(prefix="ffst_build_") as tmpdir:
+        objs, cmds = [], []
+        for s in SOURCES:
+            obj = os.path.join(tmpdir, s.replace(".hip", ".o"))
+            objs.append(obj)
+            cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, s), "-o", obj])
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as pool:
+            results = list(pool.map(_run, cmds))
+        for cmd, (rc, err) in zip(cmds, results):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if rc != 0:
+                raise RuntimeError("hipcc failed:\n" + err)
+            if verbose and err.strip():
+                print(err, file=sys.stderr)
+        tmp = LIB + ".tmp"
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        rc, err = _run(link)
+        if rc != 0:
+            raise RuntimeError("link failed:\n" + err)
     os.replace(tmp, LIB)
     return LIB
 

@@ -32,9 +32,14 @@ struct ffst_plan {
   int2* d_lines = nullptr;      // forward column lines (spectrum, column), by spectrum
   int* d_col_ptr = nullptr;     // per plane group: columns -> spectra (CSR, absolute pointers)
   int* d_col_planes = nullptr;
+  // complex shearlets: compact one-sided spectra over cyclic full-plane windows
+  float* psip = nullptr;        // plane i: w[i] columns of M values at psip + poff[i]
+  long long* d_poff = nullptr;
+  int2* d_col_ent = nullptr;    // adjoint CSR entries (spectrum, 4 * window column + flags)
   // host copies
   std::vector<int> lo, w;
   std::vector<long long> off;
+  std::vector<long long> poff;
   long long zimg = 0;           // complex elements of one image's compact buffer
   std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
   std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
@@ -66,7 +71,8 @@ bool plan_ok(const ffst_plan* p) { return p && p->magic == kMagic; }
 const char* kKernelNames[KID_COUNT] = {
     "k_spectra", "k_windows", "k_r2c_rows(image)", "k_col_fft(image)", "k_fwd_cols",
     "k_c2r_rows(planes)", "k_r2c_rows(planes)", "k_adj_cols", "k_col_fft(inverse)",
-    "k_c2r_rows(image)", "k_expand"};
+    "k_c2r_rows(image)", "k_expand", "k_one_sided", "k_fwd_cols(complex)", "k_c2c_rows(planes, inverse)",
+    "k_c2c_rows(planes)", "k_adj_cols(complex)"};
 
 struct ProfRec {
   int id;
@@ -154,6 +160,11 @@ std::vector<float2> twiddles(int L) {
   return t;
 }
 
+// Frees device memory whose release status no caller can act on.
+void release(void* ptr) {
+  if (ptr) (void)hipFree(ptr);
+}
+
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& src) {
   *dst = nullptr;
@@ -166,9 +177,9 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
-                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes};
+                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent};
   for (void* b : bufs)
-    if (b) hipFree(b);
+    if (b) release(b);
   p->magic = 0;
   delete p;
 }
@@ -197,6 +208,8 @@ Schedule schedule(const ffst_plan* p, int batch) {
   // row kernels index rows and images with 32-bit integers
   const long long rows_per_img = (long long)p->eta * p->M;
   sc.chunk_imgs = (int)std::max(1LL, std::min<long long>(sc.chunk_imgs, (1LL << 30) / rows_per_img));
+  // and recover (image, plane) from a float reciprocal, exact below 2^20 planes
+  sc.chunk_imgs = std::max(1, std::min(sc.chunk_imgs, (1 << 20) / p->eta));
   sc.chunk_imgs = std::max(1, std::min(sc.chunk_imgs, std::max(batch, 1)));
   // adjoint column lines per unit; below ~2 lines per SIMD the spectra of a
   // column are split over several lines (partial sums)
@@ -249,6 +262,80 @@ int launched(hipError_t e, const char* what) {
   return FFST_OK;
 }
 
+// Smallest cyclic range of columns holding every flagged column: the
+// complement of the longest cyclic run of unflagged columns (the first such
+// run on ties). w = 0 for no flagged column.
+void cyclic_window(const unsigned char* f, int N, int* lo, int* w) {
+  int best = -1, start = 0, nflag = 0;
+  for (int c = 0; c < N; ++c) nflag += f[c] != 0;
+  if (nflag == 0) {
+    *lo = 0;
+    *w = 0;
+    return;
+  }
+  if (nflag == N) {
+    *lo = 0;
+    *w = N;
+    return;
+  }
+  for (int s = 0; s < N; ++s) {
+    if (f[s] || !f[(s + N - 1) % N]) continue;  // not the start of an unflagged run
+    int len = 0;
+    while (!f[(s + len) % N]) ++len;
+    if (len > best) {
+      best = len;
+      start = s;
+    }
+  }
+  *lo = (start + best) % N;
+  *w = N - best;
+}
+
+// Complex shearlets: windows of the one-sided spectra from their column
+// flags, then the compact float32 spectra (evaluated in float64). The half-
+// plane real spectra are released afterwards.
+hipError_t one_sided_spectra(ffst_plan* p, const GenParams& g, const int* d_kind, const int* d_j, const int* d_k) {
+  const int M = p->M, N = p->N, eta = p->eta;
+  unsigned char* d_flags = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_flags), (size_t)eta * N);
+  if (e != hipSuccess) return e;
+  e = timed(KID_ONE_SIDED, nullptr,
+            [&] { return launch_one_sided_flags(p->psi, M, N, eta, d_kind, d_j, d_k, d_flags, nullptr); });
+  std::vector<unsigned char> flags((size_t)eta * N);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost);
+  release(d_flags);
+  if (e != hipSuccess) return e;
+  p->poff.assign(eta, 0);
+  long long total = 0;
+  int max_w = 0;
+  for (int i = 0; i < eta; ++i) {
+    cyclic_window(flags.data() + (size_t)i * N, N, &p->lo[i], &p->w[i]);
+    p->poff[i] = total;
+    total += (long long)p->w[i] * M;
+    max_w = std::max(max_w, p->w[i]);
+  }
+  if ((e = upload(&p->d_lo, p->lo)) != hipSuccess || (e = upload(&p->d_w, p->w)) != hipSuccess ||
+      (e = upload(&p->d_poff, p->poff)) != hipSuccess)
+    return e;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&p->psip), (size_t)std::max(total, 1LL) * sizeof(float))) != hipSuccess)
+    return e;
+  e = timed(KID_ONE_SIDED, nullptr, [&] {
+    return launch_one_sided_pack(g, eta, max_w, d_kind, d_j, d_k, p->d_lo, p->d_w, p->d_poff, p->psip, nullptr);
+  });
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) {
+    release(p->psi);
+    p->psi = nullptr;
+  }
+  return e;
+}
+
+int reject_kind(const ffst_plan* p, bool want_complex, const char* call) {
+  if (p->opt.complex_shearlets == (want_complex ? 1 : 0)) return FFST_OK;
+  return fail(FFST_EINVAL, "%s: the plan has %s shearlets", call, want_complex ? "real" : "complex");
+}
+
 Windows plane_windows(const ffst_plan* p) { return Windows{p->d_lo, p->d_w, p->d_off}; }
 Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_w, p->d_img_off}; }
 
@@ -267,6 +354,8 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   if (o.max_scale_min != 0 && o.max_scale_min != 1) return fail(FFST_EINVAL, "max_scale_min must be 0 or 1");
   if (o.shearlet != FFST_SHEARLET_MEYER && o.shearlet != FFST_SHEARLET_MEYER_SMOOTH)
     return fail(FFST_EINVAL, "unknown shearlet %d", o.shearlet);
+  if (o.complex_shearlets != 0 && o.complex_shearlets != 1)
+    return fail(FFST_EINVAL, "complex_shearlets must be 0 or 1");
   if (J <= 0) J = default_scales(M, N);
   if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
   if (!is_pow2(M) || !is_pow2(N) || M < 8 || N < 8 || M > 4096 || N > 4096 || !supported_length(M))
@@ -311,42 +400,51 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       (e = upload(&d_kind, kind)) != hipSuccess || (e = upload(&d_j, jj)) != hipSuccess ||
       (e = upload(&d_k, kk)) != hipSuccess || (e = upload(&d_lo, lo_init)) != hipSuccess ||
       (e = upload(&d_hi, hi_init)) != hipSuccess) {
-    hipFree(d_kind); hipFree(d_j); hipFree(d_k); hipFree(d_lo); hipFree(d_hi);
+    release(d_kind); release(d_j); release(d_k); release(d_lo); release(d_hi);
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
   GenParams g{M, N, p->delta, o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? 1 : 0};
+  const bool cplx = o.complex_shearlets == 1;
   e = timed(KID_SPECTRA, nullptr, [&] { return launch_spectra(g, p->eta, d_kind, d_j, d_k, p->psi, nullptr); });
-  if (e == hipSuccess)
+  if (e == hipSuccess && !cplx)
     e = timed(KID_WINDOWS, nullptr, [&] { return launch_windows(p->psi, M, N, p->eta, d_lo, d_hi, nullptr); });
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  std::vector<int> hi(p->eta);
   p->lo.assign(p->eta, 0);
-  if (e == hipSuccess) e = hipMemcpy(p->lo.data(), d_lo, p->eta * sizeof(int), hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(hi.data(), d_hi, p->eta * sizeof(int), hipMemcpyDeviceToHost);
-  hipFree(d_kind); hipFree(d_j); hipFree(d_k); hipFree(d_lo); hipFree(d_hi);
+  p->w.assign(p->eta, 0);
+  if (e == hipSuccess && cplx) {
+    e = one_sided_spectra(p, g, d_kind, d_j, d_k);
+  } else if (e == hipSuccess) {
+    std::vector<int> hi(p->eta);
+    e = hipMemcpy(p->lo.data(), d_lo, p->eta * sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hi.data(), d_hi, p->eta * sizeof(int), hipMemcpyDeviceToHost);
+    for (int i = 0; i < p->eta; ++i) {
+      if (hi[i] < p->lo[i]) {  // all-zero plane
+        p->lo[i] = 0;
+        p->w[i] = 0;
+      } else {
+        p->w[i] = hi[i] - p->lo[i] + 1;
+      }
+    }
+  }
+  release(d_kind); release(d_j); release(d_k); release(d_lo); release(d_hi);
   if (e != hipSuccess) {
     free_plan(p);
     return fail(FFST_EDEVICE, "spectra generation: %s", hipGetErrorString(e));
   }
 
   // Compact per-plane windows and the work lists of the column kernels.
-  p->w.assign(p->eta, 0);
+  // Real shearlets: half-plane columns [lo, lo + w). Complex shearlets:
+  // cyclic full-plane columns (lo + m) mod N, m < w.
   p->off.assign(p->eta, 0);
   p->line_ptr.assign(p->eta + 1, 0);
   std::vector<int2> lines;
   long long acc = 0;
   for (int i = 0; i < p->eta; ++i) {
-    if (hi[i] < p->lo[i]) {  // all-zero plane
-      p->lo[i] = 0;
-      p->w[i] = 0;
-    } else {
-      p->w[i] = hi[i] - p->lo[i] + 1;
-    }
     p->off[i] = acc;
     acc += (long long)p->pitch * p->w[i];
     p->line_ptr[i] = (int)lines.size();
-    for (int c = p->lo[i]; c < p->lo[i] + p->w[i]; ++c) lines.push_back(make_int2(i, c));
+    for (int m = 0; m < p->w[i]; ++m) lines.push_back(make_int2(i, cplx ? m : p->lo[i] + m));
   }
   p->line_ptr[p->eta] = (int)lines.size();
   p->zimg = acc;
@@ -368,29 +466,52 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   }
   p->groups.push_back(p->eta);
   const int ngroups = (int)p->groups.size() - 1;
-  // Within a group, order the forward lines by column so that the lines that
-  // read the same column of F run next to each other.
+  // Within a group, order the forward lines by the column of F they read so
+  // that the lines that read the same column run next to each other.
+  auto f_col = [p, cplx](const int2& l) {
+    if (!cplx) return l.y;
+    const int c = (p->lo[l.x] + l.y) % p->N;
+    return c <= p->N / 2 ? c : p->N - c;
+  };
   for (int g = 0; g < ngroups; ++g)
     std::stable_sort(lines.begin() + p->line_ptr[p->groups[g]], lines.begin() + p->line_ptr[p->groups[g + 1]],
-                     [](const int2& a, const int2& b) { return a.y < b.y; });
+                     [&](const int2& a, const int2& b) { return f_col(a) < f_col(b); });
 
-  // Adjoint: column -> spectra whose window holds it, one CSR per plane group.
+  // Adjoint: half-plane column -> spectra whose window holds it, one CSR per
+  // plane group. Complex shearlets: entries (i, 4 m + flags) for the window
+  // column m that is c (flag 1) or N - c (flag 2); both flags when c = N - c
+  // mod N.
   std::vector<int> col_ptr, col_planes;
+  std::vector<int2> col_ent;
   for (int g = 0; g < ngroups; ++g) {
-    col_ptr.push_back((int)col_planes.size());
+    col_ptr.push_back(cplx ? (int)col_ent.size() : (int)col_planes.size());
     for (int c = 0; c < p->H; ++c) {
-      for (int i = p->groups[g]; i < p->groups[g + 1]; ++i)
-        if (p->w[i] > 0 && c >= p->lo[i] && c < p->lo[i] + p->w[i]) col_planes.push_back(i);
-      col_ptr.push_back((int)col_planes.size());
+      for (int i = p->groups[g]; i < p->groups[g + 1]; ++i) {
+        if (p->w[i] == 0) continue;
+        if (!cplx) {
+          if (c >= p->lo[i] && c < p->lo[i] + p->w[i]) col_planes.push_back(i);
+          continue;
+        }
+        const int c2 = (p->N - c) % p->N;
+        const int m1 = ((c - p->lo[i]) % p->N + p->N) % p->N;
+        const int m2 = ((c2 - p->lo[i]) % p->N + p->N) % p->N;
+        if (c2 == c) {
+          if (m1 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m1 + 3));
+        } else {
+          if (m1 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m1 + 1));
+          if (m2 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m2 + 2));
+        }
+      }
+      col_ptr.push_back(cplx ? (int)col_ent.size() : (int)col_planes.size());
     }
   }
   std::vector<int> img_lo{0}, img_w{p->H};
   std::vector<long long> img_off{0};
-  if ((e = upload(&p->d_lo, p->lo)) != hipSuccess || (e = upload(&p->d_w, p->w)) != hipSuccess ||
-      (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
+  if ((!p->d_lo && (e = upload(&p->d_lo, p->lo)) != hipSuccess) ||
+      (!p->d_w && (e = upload(&p->d_w, p->w)) != hipSuccess) || (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
       (e = upload(&p->d_lines, lines)) != hipSuccess || (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
-      (e = upload(&p->d_col_planes, col_planes)) != hipSuccess) {
+      (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
@@ -416,6 +537,14 @@ int ffst_get_spectra(const ffst_plan* p, float* dst, int full_plane) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (!dst) return fail(FFST_EINVAL, "dst must be non-NULL");
   if (full_plane != 0 && full_plane != 1) return fail(FFST_EINVAL, "full_plane must be 0 or 1");
+  if (p->opt.complex_shearlets) {
+    if (!full_plane) return fail(FFST_EINVAL, "one-sided spectra are only available on the full plane");
+    hipError_t e = timed(KID_EXPAND, nullptr, [&] {
+      return launch_one_sided_expand(p->psip, p->M, p->N, p->eta, p->d_lo, p->d_w, p->d_poff, dst, nullptr);
+    });
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return launched(e, "ffst_get_spectra");
+  }
   const int cols = full_plane ? p->N : p->H;
   hipError_t e = timed(KID_EXPAND, nullptr, [&] { return launch_expand(p->psi, p->M, p->N, p->eta, cols, dst, nullptr); });
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -427,13 +556,14 @@ int ffst_plan_windows(const ffst_plan* p, int* first_col, int* last_col) {
   if (!first_col || !last_col) return fail(FFST_EINVAL, "outputs must be non-NULL");
   for (int i = 0; i < p->eta; ++i) {
     first_col[i] = p->w[i] ? p->lo[i] : -1;
-    last_col[i] = p->w[i] ? p->lo[i] + p->w[i] - 1 : -1;
+    last_col[i] = p->w[i] ? (p->lo[i] + p->w[i] - 1) % (p->opt.complex_shearlets ? p->N : p->H) : -1;
   }
   return ok();
 }
 
 int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (reject_kind(p, false, "ffst_forward") != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
   int st = check_call(p, f, img * (size_t)std::max(batch, 0), coeffs, img * p->eta * (size_t)std::max(batch, 0),
                       batch, ws);
@@ -475,6 +605,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
 
 int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (reject_kind(p, false, "ffst_adjoint") != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
   int st = check_call(p, coeffs, img * p->eta * (size_t)std::max(batch, 0), f, img * (size_t)std::max(batch, 0),
                       batch, ws);
@@ -521,9 +652,101 @@ int ffst_inverse(const ffst_plan* p, const float* coeffs, float* f, int batch, v
   return ffst_adjoint(p, coeffs, f, batch, ws, stream);
 }
 
+int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (reject_kind(p, true, "ffst_forward_complex") != FFST_OK) return FFST_EINVAL;
+  const size_t img = (size_t)p->M * p->N * sizeof(float);
+  const size_t nb = (size_t)std::max(batch, 0);
+  int st = check_call(p, f, img * nb, coeffs, 2 * img * p->eta * nb, batch, ws);
+  if (st != FFST_OK || batch == 0) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Schedule sc = schedule(p, batch);
+  float2* F = static_cast<float2*>(ws);
+  float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
+  float2* C = reinterpret_cast<float2*>(coeffs);
+  const long long MH = (long long)p->pitch * p->H;
+  const long long MN = (long long)p->M * p->N;
+  const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
+
+  RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
+  hipError_t e = timed(KID_R2C_IMAGE, s, [&] { return launch_r2c_rows(ra, s); });
+  if (e == hipSuccess)
+    e = timed(KID_FFT_COLS_IMAGE, s,
+              [&] { return launch_line_fft(p->M, F, batch * p->H, p->pitch, false, nullptr, 0, 0, p->twM, s); });
+  const int ngroups = (int)p->groups.size() - 1;
+  for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
+    const int nimg = std::min(sc.chunk_imgs, batch - img0);
+    for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
+      const int p0 = p->groups[g], p1 = p->groups[g + 1];
+      const long long base = p->off[p0];
+      const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
+      CFwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psip, p->d_poff, p->d_lines + p->line_ptr[p0],
+                      p->line_ptr[p1] - p->line_ptr[p0], nimg, p->pitch, plane_windows(p), unit_stride, base, Y,
+                      scale, p->twM};
+      e = timed(KID_FWD_COLS_C, s, [&] { return launch_fwd_lines_c(fa, s); });
+      if (e != hipSuccess) break;
+      CRowArgs rc{C + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
+                  p->M, p->N, p->pitch, plane_windows(p), p->twN};
+      e = timed(KID_C2C_PLANES_INV, s, [&] { return launch_c2c_rows_inv(rc, s); });
+    }
+  }
+  return launched(e, "ffst_forward_complex");
+}
+
+int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (reject_kind(p, true, "ffst_adjoint_complex") != FFST_OK) return FFST_EINVAL;
+  const size_t img = (size_t)p->M * p->N * sizeof(float);
+  const size_t nb = (size_t)std::max(batch, 0);
+  int st = check_call(p, coeffs, 2 * img * p->eta * nb, f, img * nb, batch, ws);
+  if (st != FFST_OK || batch == 0) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Schedule sc = schedule(p, batch);
+  float2* A = static_cast<float2*>(ws);
+  float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
+  float2* P = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes + sc.yz_bytes);
+  float2* C = reinterpret_cast<float2*>(const_cast<float*>(coeffs));
+  const long long MH = (long long)p->pitch * p->H;
+  const long long MN = (long long)p->M * p->N;
+  // 1/(M N) of the inverse DFT and 1/2 of the Hermitian part
+  const float scale = (float)(0.5 / ((double)p->M * (double)p->N));
+  const int ngroups = (int)p->groups.size() - 1;
+  hipError_t e = hipSuccess;
+  for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
+    const int nimg = std::min(sc.chunk_imgs, batch - img0);
+    for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
+      const int p0 = p->groups[g], p1 = p->groups[g + 1];
+      const long long base = p->off[p0];
+      const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
+      CRowArgs rr{C + img0 * p->eta * MN, Z, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
+                  p->M, p->N, p->pitch, plane_windows(p), p->twN};
+      e = timed(KID_C2C_PLANES_FWD, s, [&] { return launch_c2c_rows_fwd(rr, s); });
+      if (e != hipSuccess) break;
+      CAdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psip, p->d_poff,
+                      p->d_col_ptr + g * (p->H + 1), p->d_col_ent, nimg, sc.nparts, g > 0 ? 1 : 0,
+                      sc.fused ? 1 : 0, p->pitch, sc.fused ? A + img0 * MH : P, scale, p->twM};
+      e = timed(KID_ADJ_COLS_C, s, [&] { return launch_adj_lines_c(aa, s); });
+    }
+    if (e == hipSuccess && !sc.fused)
+      e = timed(KID_IFFT_COLS_IMAGE, s, [&] {
+        return launch_line_fft(p->M, A + img0 * MH, nimg * p->H, p->pitch, true, P, sc.nparts,
+                               (long long)nimg * MH, p->twM, s);
+      });
+  }
+  if (e == hipSuccess) {
+    RowArgs rc{f, A, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
+    e = timed(KID_C2R_IMAGE, s, [&] { return launch_c2r_rows(rc, s); });
+  }
+  return launched(e, "ffst_adjoint_complex");
+}
+
+int ffst_inverse_complex(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  return ffst_adjoint_complex(p, coeffs, f, batch, ws, stream);
+}
+
 void ffst_destroy(ffst_plan* p) {
   if (!plan_ok(p)) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   free_plan(p);
 }
 

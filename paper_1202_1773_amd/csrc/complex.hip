@@ -1,0 +1,431 @@
+// complex.hip -- the FFST with complex shearlets (one-sided spectra, Sec. 3.8.2).
+//
+// Coefficients: c_i = ifft2(Psi+_i * fft2(f)), complex, for a real image f.
+// Psi+_i is not even, so the coefficient rows are complex and the row pass is
+// a complex FFT of length N over the full plane. The image spectrum F is
+// still kept on the half plane (f is real): full-plane column c > N/2 is
+// read as conj F(-r, N - c). Psi+_i is stored compactly over a cyclic range
+// of full-plane columns (one lobe, plus the Nyquist values that stay two-
+// sided), so the intermediates Y_i / Z_i hold only those columns.
+//
+// Forward: the image passes of the real transform give F on the half plane;
+// k_fwd_lines_c multiplies each window column of Psi+_i by the matching
+// (possibly mirrored) column of F / (M N) and runs the inverse column FFT into
+// Y_i; k_c2c_rows_inv runs the inverse row FFT over the window columns and
+// writes full complex rows of c_i.
+//
+// Adjoint (for real images): Re sum_i ifft2(Psi+_i fft2(c_i)). With
+// X = sum_i Psi+_i fft2(c_i) this is the inverse DFT of the Hermitian part
+// (X(w) + conj X(-w)) / 2, whose half plane the real transform's last passes
+// turn into the image. k_c2c_rows_fwd runs the forward row FFT of each
+// coefficient row and stores its window columns Z_i; k_adj_lines_c, per
+// half-plane column c, transforms along the column every Z_i column that is
+// c or N - c, multiplies by Psi+_i and accumulates both sums in registers,
+// then forms (X(r, c) + conj X(-r, N - c)) / 2 through LDS.
+#include "fft_core.hpp"
+#include "internal.hpp"
+#include "launch_cfg.hpp"
+
+namespace ffst {
+namespace {
+
+struct CRowJob {
+  float2* x;                // complex rows: (img, plane, r) at x + img*x_img_stride + (plane*M + r)*L
+  float2* z;                // window columns: (img, plane, m, r) at z + img*z_img_stride +
+                            //   (win.off[plane] - z_off_base) + m*zp + r
+  long long x_img_stride, z_img_stride, z_off_base;
+  int nimg, nplanes, plane0, M, rb, zp;
+  float inv_nplanes;
+  Windows win;
+  const float2* twN;        // exp(-2 pi i m / L), m < L
+};
+
+// Inverse row FFT: the window columns of each row become a full complex row.
+template <int L>
+__global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_inv(CRowJob job) {
+  using C = CRowCfg<L>;
+  constexpr int V = C::V, G = C::G, NT = C::THREADS;
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  const int g = threadIdx.x / G;          // row slot (FFT phase)
+  const int j = threadIdx.x % G;
+  const int rb = job.rb;
+  const int tr = threadIdx.x % rb;        // row (transpose phase)
+  const int tc = threadIdx.x / rb;        // first column (transpose phase)
+  const int cstep = NT / rb;
+  const bool row_ok = g < rb;
+  float2* my = lds + g * C::STRIDE;
+  float2* zr = lds + tr * C::STRIDE;
+  TwiddleRegs<L, V> tw;
+  tw.load(j, job.twN, 1);
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+
+  // columns k = tc + cstep * m of row tr (zero outside the window); V values
+  // cover the row since cstep * V >= L
+  auto load_cols = [&](int u, float2 (&dst)[V]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    const float2* in = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+      const int k = tc + cstep * m;
+      const int cm = (k - lo) & (L - 1);
+      dst[m] = (k < L && cm < w) ? in[(long long)cm * job.zp] : make_float2(0.f, 0.f);
+    }
+  };
+
+  float2 nxt[V];
+  int u = blockIdx.x;
+  if (u < nunits) load_cols(u, nxt);
+  for (; u < nunits; u += gridDim.x) {
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+      const int k = tc + cstep * m;
+      if (k < L) zr[lpad<V>(k)] = nxt[m];
+    }
+    __syncthreads();
+    if (u + (int)gridDim.x < nunits) load_cols(u + gridDim.x, nxt);
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = my[lpad<V>(j + G * s)];
+    lds_sync<C::SYNC>();
+    fft_group<L, V, true, C::SYNC>(v, j, my, tw);
+    if (row_ok) {
+      const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+      float2* yr = job.x + ru.img * job.x_img_stride + ((long long)ru.plane * job.M + ru.r0 + g) * L;
+#pragma unroll
+      for (int s = 0; s < V; ++s) yr[j + G * s] = v[s];
+    }
+    __syncthreads();
+  }
+}
+
+// Forward row FFT of full complex rows; the window columns are stored
+// column-contiguous (rb consecutive rows per column).
+template <int L>
+__global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob job) {
+  using C = CRowCfg<L>;
+  constexpr int V = C::V, G = C::G, NT = C::THREADS;
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  const int rb = job.rb;
+  const int tr = threadIdx.x % rb;
+  const int tc = threadIdx.x / rb;
+  const int cstep = NT / rb;
+  const bool row_ok = g < rb;
+  float2* my = lds + g * C::STRIDE;
+  const float2* zr = lds + tr * C::STRIDE;
+  TwiddleRegs<L, V> tw;
+  tw.load(j, job.twN, 1);
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+
+  auto load_rows = [&](int u, float2 (&dst)[V]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const float2* xr = job.x + ru.img * job.x_img_stride +
+                       ((long long)ru.plane * job.M + ru.r0 + (row_ok ? g : 0)) * L;
+#pragma unroll
+    for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+  };
+
+  float2 nxt[V];
+  int u = blockIdx.x;
+  if (u < nunits) load_rows(u, nxt);
+  for (; u < nunits; u += gridDim.x) {
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = nxt[s];
+    if (u + (int)gridDim.x < nunits) load_rows(u + gridDim.x, nxt);
+    fft_group<L, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+    for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = v[s];
+    __syncthreads();
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    float2* out = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+#pragma unroll 4
+    for (int m = tc; m < w; m += cstep) out[(long long)m * job.zp] = zr[lpad<V>((lo + m) & (L - 1))];
+    __syncthreads();
+  }
+}
+
+struct CFwdLineJob {
+  const float2* F;          // [nimg][H][pitch]
+  const float* psip;
+  const long long* poff;
+  const int2* lines;        // (spectrum, window column m), image lines ordered by the F column they read
+  int nlines, nimg, H, N;
+  int pitch;
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+
+// Y_i[m] = ifft_col(Psi+_i[m] * scale * F[c]) with c = (lo_i + m) mod N; for
+// c > N/2 the column of F is conj F(-r, N - c).
+template <int M>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.nlines * job.nimg;
+  float2 fn[V];
+  float pn[V];
+  auto load_unit = [&](int u) {
+    const int q = u * C::LPB + g;
+    const int qq = q < total ? q : 0;
+    const int img = qq / job.nlines;
+    const int2 ln = job.lines[qq % job.nlines];
+    const int c = (job.win.lo[ln.x] + ln.y) & (job.N - 1);
+    const bool upper = c > job.N / 2;
+    const float2* fb = job.F + ((long long)img * job.H + (upper ? job.N - c : c)) * job.pitch;
+    const float* pb = job.psip + job.poff[ln.x] + (long long)ln.y * M;
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      const int r = j + G * s;
+      const float2 fv = fb[upper ? ((M - r) & (M - 1)) : r];
+      fn[s] = upper ? conjf2(fv) : fv;
+      pn[s] = pb[r];
+    }
+  };
+  int u = blockIdx.x;
+  if (u * C::LPB < total) load_unit(u);
+  for (; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int img = qq / job.nlines;
+    const int2 ln = job.lines[qq % job.nlines];
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = cscale(fn[s], pn[s] * job.scale);
+    if ((u + (int)gridDim.x) * C::LPB < total) load_unit(u + gridDim.x);
+    fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
+    if (ok) {
+      float2* yb = job.Y + img * job.y_img_stride + (job.win.off[ln.x] - job.y_off_base) + (long long)ln.y * job.pitch;
+#pragma unroll
+      for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
+    }
+  }
+}
+
+struct CAdjLineJob {
+  const float2* Z;
+  long long z_img_stride, z_off_base;
+  Windows win;
+  const float* psip;
+  const long long* poff;
+  const int* col_ptr;
+  const int2* col_ent;
+  int H, nimg, nparts;
+  int pitch;
+  int accumulate;
+  float2* out;              // FUSED: A [nimg][H][pitch]; else partial sums [nparts][nimg][H][pitch]
+  float scale;              // 1 / (2 M N)
+  const float2* twM;
+};
+
+// Line (img, c, part): X1 = sum Psi+_i[m] fft_col(Z_i[m]) over the entries
+// whose column is c, X2 the same over the entries whose column is N - c
+// (part p takes every nparts-th entry); A[c](r) = scale * (X1(r) + conj X2(-r)).
+template <int M, bool FUSED>
+__device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  float2* my = lds + g * C::STRIDE;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.H * job.nimg * job.nparts;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int part = qq % job.nparts;
+    const int rest = qq / job.nparts;
+    const int img = rest % job.nimg;
+    const int c = rest / job.nimg;
+    float2 acc1[V], acc2[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc1[s] = acc2[s] = make_float2(0.f, 0.f);
+    const float2* zimg = job.Z + img * job.z_img_stride - job.z_off_base;
+    const int q1 = ok ? job.col_ptr[c + 1] : 0;
+    int t = job.col_ptr[c] + part;
+    float2 zn[V];
+    float pn[V];
+    int fn = 0;
+    auto load_entry = [&](int tt) {
+      const int2 e = job.col_ent[tt];
+      const int m = e.y >> 2;
+      fn = e.y & 3;
+      const float2* zb = zimg + job.win.off[e.x] + (long long)m * job.pitch;
+      const float* pb = job.psip + job.poff[e.x] + (long long)m * M;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        zn[s] = zb[j + G * s];
+        pn[s] = pb[j + G * s];
+      }
+    };
+    if (t < q1) load_entry(t);
+    for (; t < q1; t += job.nparts) {
+      float2 v[V];
+      float ps[V];
+      const int fl = fn;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        v[s] = zn[s];
+        ps[s] = pn[s];
+      }
+      if (t + job.nparts < q1) load_entry(t + job.nparts);
+      fft_group<M, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        const float2 pv = cscale(v[s], ps[s]);
+        if (fl & 1) acc1[s] = cadd(acc1[s], pv);
+        if (fl & 2) acc2[s] = cadd(acc2[s], pv);
+      }
+    }
+    // Hermitian part: acc1(r) + conj acc2(-r mod M)
+#pragma unroll
+    for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = acc2[s];
+    lds_sync<C::SYNC>();
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      const float2 rv = my[lpad<V>((M - (j + G * s)) & (M - 1))];
+      acc1[s] = cscale(cadd(acc1[s], conjf2(rv)), job.scale);
+    }
+    lds_sync<C::SYNC>();
+    if constexpr (FUSED) {
+      fft_group<M, V, true, C::SYNC>(acc1, j, my, tw);
+      if (ok) {
+        float2* ab = job.out + ((long long)img * job.H + c) * job.pitch;
+#pragma unroll
+        for (int s = 0; s < V; ++s) ab[j + G * s] = acc1[s];
+      }
+    } else if (ok) {
+      float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * job.pitch;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        float2 val = acc1[s];
+        if (job.accumulate) val = cadd(val, pb[j + G * s]);
+        pb[j + G * s] = val;
+      }
+    }
+  }
+}
+
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_c(CAdjLineJob job) {
+  adj_lines_c_body<M, FUSED>(job);
+}
+
+// Complex row kernels take the full length N, line kernels the length M.
+#define FFST_CROW_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define FFST_CCOL_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+CRowJob make_crow_job(const CRowArgs& a, int rb_max) {
+  CRowJob j;
+  j.x = a.x;
+  j.z = a.z;
+  j.x_img_stride = a.x_img_stride;
+  j.z_img_stride = a.z_img_stride;
+  j.z_off_base = a.z_off_base;
+  j.nimg = a.nimg;
+  j.nplanes = a.nplanes;
+  j.plane0 = a.plane0;
+  j.M = a.M;
+  j.rb = a.M < rb_max ? a.M : rb_max;
+  j.zp = a.zp;
+  j.inv_nplanes = 1.0f / (float)a.nplanes;
+  j.win = a.win;
+  j.twN = a.twN;
+  return j;
+}
+
+}  // namespace
+
+hipError_t launch_c2c_rows_inv(const CRowArgs& a, hipStream_t s) {
+  if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  switch (a.N) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const CRowJob job = make_crow_job(a, CRowCfg<n>::RB);                                         \
+    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
+    hipLaunchKernelGGL(k_c2c_rows_inv<n>, dim3(grid_for(units, CRowCfg<n>::THREADS)),             \
+                       dim3(CRowCfg<n>::THREADS), 0, s, job);                                     \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_CROW_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_c2c_rows_fwd(const CRowArgs& a, hipStream_t s) {
+  if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  switch (a.N) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const CRowJob job = make_crow_job(a, CRowCfg<n>::RB);                                         \
+    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
+    hipLaunchKernelGGL(k_c2c_rows_fwd<n>, dim3(grid_for(units, CRowCfg<n>::THREADS)),             \
+                       dim3(CRowCfg<n>::THREADS), 0, s, job);                                     \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_CROW_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fwd_lines_c(const CFwdLineArgs& a, hipStream_t s) {
+  CFwdLineJob job{a.F, a.psip, a.poff, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.N, a.pitch, a.win,
+                  a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
+  if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.nlines * job.nimg;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    hipLaunchKernelGGL(k_fwd_lines_c<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),              \
+                       dim3(LineCfg<n>::THREADS), 0, s, job);                                     \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_CCOL_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s) {
+  CAdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psip, a.poff, a.col_ptr, a.col_ent, a.N / 2 + 1,
+                  a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
+  if (job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.H * job.nimg * job.nparts;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
+    if (a.fused)                                                                                  \
+      hipLaunchKernelGGL((k_adj_lines_c<n, true>), grid, block, 0, s, job);                       \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_adj_lines_c<n, false>), grid, block, 0, s, job);                      \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_CCOL_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ffst

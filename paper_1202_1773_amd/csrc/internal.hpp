@@ -36,6 +36,11 @@ enum KernelId : int {
   KID_IFFT_COLS_IMAGE,
   KID_C2R_IMAGE,
   KID_EXPAND,
+  KID_ONE_SIDED,            // one-sided spectra: column flags and packing
+  KID_FWD_COLS_C,           // complex path: column lines of the forward
+  KID_C2C_PLANES_INV,       //   inverse complex row FFTs writing the coefficients
+  KID_C2C_PLANES_FWD,       //   forward complex row FFTs of the coefficients
+  KID_ADJ_COLS_C,           //   column lines of the adjoint
   KID_COUNT
 };
 
@@ -44,6 +49,13 @@ hipError_t launch_spectra(const GenParams& g, int eta, const int* kind, const in
                           float* psi, hipStream_t s);
 hipError_t launch_windows(const float* psi, int M, int N, int eta, int* lo, int* hi, hipStream_t s);
 hipError_t launch_expand(const float* psi, int M, int N, int eta, int cols, float* out, hipStream_t s);
+hipError_t launch_one_sided_flags(const float* psi, int M, int N, int eta, const int* kind, const int* jj,
+                                  const int* kk, unsigned char* flags, hipStream_t s);
+hipError_t launch_one_sided_pack(const GenParams& g, int eta, int max_w, const int* kind, const int* jj,
+                                 const int* kk, const int* lo, const int* w, const long long* poff, float* psip,
+                                 hipStream_t s);
+hipError_t launch_one_sided_expand(const float* psip, int M, int N, int eta, const int* lo, const int* w,
+                                   const long long* poff, float* out, hipStream_t s);
 
 // Row transforms of length N = 2L. The rows of a unit are (img, plane, r) for
 // img < nimg, plane0 <= plane < plane0 + nplanes, r < M; real row
@@ -98,6 +110,62 @@ struct AdjLineArgs {
   const float2* twM;
 };
 hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s);
+
+// ---- complex (one-sided) shearlets ----
+//
+// Windows are cyclic ranges of full-plane columns: plane i holds the columns
+// (lo[i] + m) mod N for m < w[i]; column m of (img, plane) sits at
+// z + img*z_img_stride + (win.off[plane] - z_off_base) + m*zp, and the
+// compact one-sided spectrum's column m at psip + poff[plane] + m*M.
+
+// Complex rows of length N; row (img, plane, r) of the coefficients starts
+// at x + img*x_img_stride + (plane*M + r)*N (complex elements).
+struct CRowArgs {
+  float2* x;
+  float2* z;
+  long long x_img_stride, z_img_stride, z_off_base;
+  int nimg, nplanes, plane0, M, N;
+  int zp;
+  Windows win;
+  const float2* twN;
+};
+// Inverse row FFT of the window columns into full complex rows (unnormalised).
+hipError_t launch_c2c_rows_inv(const CRowArgs& a, hipStream_t s);
+// Forward row FFT of full complex rows, storing the window columns.
+hipError_t launch_c2c_rows_fwd(const CRowArgs& a, hipStream_t s);
+
+struct CFwdLineArgs {
+  int M, N;
+  const float2* F;          // half-plane image spectra [nimg][N/2+1][pitch]
+  const float* psip;
+  const long long* poff;
+  const int2* lines;        // (spectrum, window column m)
+  int nlines, nimg;
+  int pitch;
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+hipError_t launch_fwd_lines_c(const CFwdLineArgs& a, hipStream_t s);
+
+struct CAdjLineArgs {
+  int M, N;
+  const float2* Z;
+  long long z_img_stride, z_off_base;
+  Windows win;
+  const float* psip;
+  const long long* poff;
+  const int* col_ptr;       // half-plane column -> entries (CSR)
+  const int2* col_ent;      // (spectrum, 4 * window column + flags), flag 1: column c, 2: column N - c
+  int nimg, nparts, accumulate, fused;
+  int pitch;
+  float2* out;
+  float scale;
+  const float2* twM;
+};
+hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s);
 
 bool supported_length(int L);
 

@@ -1,0 +1,90 @@
+// launch_cfg.hpp -- lane/row/line shapes of the FFT kernels and the
+// persistent-grid sizing shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+
+namespace ffst {
+
+__host__ __device__ constexpr int line_values(int L) { return L >= 16 ? 16 : L; }
+// Column lines: 8 values per lane up to length 1024 (8*8*8 needs the same
+// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above.
+__host__ __device__ constexpr int col_values(int L) { return L > 1024 ? 16 : (L >= 8 ? 8 : L); }
+// LDS stride per line/row: congruent to 17 mod 32, so that 16 lanes reading
+// the same column of 16 rows, and 16 lanes reading 16 consecutive values of
+// one row, both touch distinct banks.
+__host__ __device__ constexpr int lds_stride(int L, int V) { return stride_mod32(lds_group_len(L, V), 17); }
+
+// Real rows of length N = 2L (complex FFT of length L), RB rows per block.
+template <int L>
+struct RowCfg {
+  static constexpr int V = line_values(L);
+  static constexpr int G = L / V;                      // lanes per row
+  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
+  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 8;
+  static constexpr int THREADS = RB * G;
+  static constexpr int STRIDE = lds_stride(L, V);
+};
+
+// Complex rows of length L (complex FFT of length L), RB rows per block; at
+// most 1024 threads and about 140 KB of LDS per block.
+template <int L>
+struct CRowCfg {
+  static constexpr int V = line_values(L);
+  static constexpr int G = L / V;
+  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
+  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 1024 / G;
+  static constexpr int THREADS = RB * G;
+  static constexpr int STRIDE = lds_stride(L, V);
+};
+
+// Contiguous lines of length L (the column direction, L = M).
+template <int L>
+struct LineCfg {
+  static constexpr int V = col_values(L);
+  static constexpr int G = L / V;
+  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
+  static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
+  static constexpr int LPB = THREADS / G;             // lines per block
+  static constexpr int STRIDE = lds_stride(L, V);
+};
+
+// Compute units of the current device (read once per process).
+inline int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      n = prop.multiProcessorCount;
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+// Persistent grids: enough blocks for the work, at most `per_cu` per CU.
+inline int grid_for(long long units, int threads) {
+  const int per_cu = threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8);
+  const long long cap = (long long)num_cus() * per_cu;
+  return (int)(units < cap ? (units > 0 ? units : 1) : cap);
+}
+
+// A unit of the row kernels: rows r0 .. r0 + rb - 1 of plane `plane` of
+// image `img`; units run image-major, then plane, then row block.
+struct RowUnit {
+  int img, plane, r0;
+};
+
+__device__ __forceinline__ RowUnit row_unit(int u, int blocks_per_plane, int nplanes, float inv_nplanes, int rb,
+                                            int plane0) {
+  RowUnit ru;
+  const int pq = u / blocks_per_plane;
+  ru.r0 = (u - pq * blocks_per_plane) * rb;
+  ru.img = (int)(((float)pq + 0.5f) * inv_nplanes);  // exact for pq < 2^20
+  ru.plane = plane0 + pq - ru.img * nplanes;
+  return ru;
+}
+
+}  // namespace ffst

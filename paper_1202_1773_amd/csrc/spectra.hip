@@ -93,6 +93,20 @@ __device__ double grid_value(const GenParams& g, int kind, int j, int k, int r, 
   return spectrum_value(kind, j, k, g.smooth, w1, w2);
 }
 
+// Grid value with the real-coefficient fix of Sec. 3.8.1, at any point
+// (r, c) of the full plane.
+__device__ double fixed_value(const GenParams& g, int kd, int j, int k, int r, int c) {
+  double val = grid_value(g, kd, j, k, r, c);
+  if (g.N % 2 == 0 && c == g.N / 2) {
+    const double b = grid_value(g, kd, j, k, (g.M - r) % g.M, c);
+    val = sqrt(0.5 * (val * val + b * b));
+  } else if (g.M % 2 == 0 && r == g.M / 2) {
+    const double b = grid_value(g, kd, j, k, r, (g.N - c) % g.N);
+    val = sqrt(0.5 * (val * val + b * b));
+  }
+  return val;
+}
+
 __global__ void __launch_bounds__(256) k_spectra(GenParams g, const int* __restrict__ kind,
                                                  const int* __restrict__ jj, const int* __restrict__ kk,
                                                  float* __restrict__ psi) {
@@ -102,16 +116,7 @@ __global__ void __launch_bounds__(256) k_spectra(GenParams g, const int* __restr
   const int i = blockIdx.y;
   if (idx >= n) return;
   const int c = (int)(idx / g.M), r = (int)(idx % g.M);
-  const int kd = kind[i], j = jj[i], k = kk[i];
-  double val = grid_value(g, kd, j, k, r, c);
-  if (g.N % 2 == 0 && c == g.N / 2) {
-    const double b = grid_value(g, kd, j, k, (g.M - r) % g.M, c);
-    val = sqrt(0.5 * (val * val + b * b));
-  } else if (g.M % 2 == 0 && r == g.M / 2) {
-    const double b = grid_value(g, kd, j, k, r, (g.N - c) % g.N);
-    val = sqrt(0.5 * (val * val + b * b));
-  }
-  psi[(long long)i * n + idx] = (float)val;
+  psi[(long long)i * n + idx] = (float)fixed_value(g, kind[i], jj[i], kk[i], r, c);
 }
 
 // First and last half-plane column holding a nonzero value, per plane:
@@ -144,7 +149,106 @@ __global__ void __launch_bounds__(256) k_expand(const float* __restrict__ psi, i
   out[(long long)i * n + idx] = psi[((long long)i * H + cc) * M + rr];
 }
 
+// ---- one-sided spectra (Sec. 3.8.2) ----
+//
+// Spectrum i >= 1 is centred on the ray of direction d = (1, -k / 2^j) in
+// (omega_1, omega_2) (h cone and seam elements) or d = (-k / 2^j, 1) (v cone).
+// Its one-sided version keeps the lobe on the side <omega, d> > 0, scaled by
+// sqrt(2), and drops the other; where a grid point and its DFT mirror are not
+// on opposite sides (the line <omega, d> = 0, and pairs on a Nyquist line)
+// the value is kept as is. The sign of <omega, d> is taken on the integer
+// frequencies: with one spacing Delta for both axes it is the sign of
+// 2^j q_N(c) - k q_M(r) (h, seam) or 2^j q_M(r) - k q_N(c) (v).
+__device__ int side_sign(int kd, int j, int k, int r, int c, int M, int N) {
+  const long long n1 = signed_freq(c, N), n2 = signed_freq(r, M);
+  const long long s = kd == KIND_V ? (-(long long)k * n1 + ((long long)1 << j) * n2)
+                                   : (((long long)1 << j) * n1 - (long long)k * n2);
+  return (s > 0) - (s < 0);
+}
+
+__device__ double one_sided_factor(int kd, int j, int k, int r, int c, int M, int N) {
+  if (kd == KIND_LOWPASS) return 1.0;
+  const int sd = side_sign(kd, j, k, r, c, M, N);
+  if (sd == 0 || side_sign(kd, j, k, (M - r) % M, (N - c) % N, M, N) != -sd) return 1.0;
+  return sd > 0 ? M_SQRT2 : 0.0;
+}
+
+// flags[i][c] = 1 if column c (full plane, c < N) of the one-sided spectrum i
+// holds a nonzero value; one block per (column, spectrum). Reads the
+// half-plane spectra (even on the grid: Psi(r, c) = Psi(-r, -c)).
+__global__ void __launch_bounds__(256) k_one_sided_flags(const float* __restrict__ psi, int M, int N,
+                                                         const int* __restrict__ kind, const int* __restrict__ jj,
+                                                         const int* __restrict__ kk, unsigned char* __restrict__ flags) {
+  const int c = blockIdx.x;
+  const int i = blockIdx.y;
+  const int H = N / 2 + 1;
+  const int kd = kind[i], j = jj[i], k = kk[i];
+  const bool upper = c >= H;
+  const float* p = psi + ((long long)i * H + (upper ? N - c : c)) * M;
+  int any = 0;
+  for (int r = threadIdx.x; r < M; r += blockDim.x) {
+    const float v = p[upper ? (M - r) % M : r];
+    any |= (v != 0.0f && one_sided_factor(kd, j, k, r, c, M, N) != 0.0);
+  }
+  const int all = __syncthreads_or(any);
+  if (threadIdx.x == 0) flags[(long long)i * N + c] = all ? 1 : 0;
+}
+
+// Compact one-sided spectra: plane i holds w[i] columns of M values starting
+// at psip + poff[i]; column m is the full-plane column (lo[i] + m) mod N.
+__global__ void __launch_bounds__(256) k_one_sided_pack(GenParams g, const int* __restrict__ kind,
+                                                        const int* __restrict__ jj, const int* __restrict__ kk,
+                                                        const int* __restrict__ lo, const int* __restrict__ w,
+                                                        const long long* __restrict__ poff, float* __restrict__ psip) {
+  const int i = blockIdx.y;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)w[i] * g.M) return;
+  const int m = (int)(idx / g.M), r = (int)(idx % g.M);
+  const int c = (lo[i] + m) % g.N;
+  const int kd = kind[i], j = jj[i], k = kk[i];
+  const double val = one_sided_factor(kd, j, k, r, c, g.M, g.N) * fixed_value(g, kd, j, k, r, c);
+  psip[poff[i] + idx] = (float)val;
+}
+
+// Row-major full-plane copy of the compact one-sided spectra.
+__global__ void __launch_bounds__(256) k_one_sided_expand(const float* __restrict__ psip, int M, int N,
+                                                          const int* __restrict__ lo, const int* __restrict__ w,
+                                                          const long long* __restrict__ poff, float* __restrict__ out) {
+  const long long n = (long long)M * N;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (idx >= n) return;
+  const int r = (int)(idx / N), c = (int)(idx % N);
+  const int m = ((c - lo[i]) % N + N) % N;
+  out[(long long)i * n + idx] = m < w[i] ? psip[poff[i] + (long long)m * M + r] : 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_one_sided_flags(const float* psi, int M, int N, int eta, const int* kind, const int* jj,
+                                  const int* kk, unsigned char* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_one_sided_flags, dim3((unsigned)N, (unsigned)eta), dim3(256), 0, s, psi, M, N, kind, jj, kk,
+                     flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_one_sided_pack(const GenParams& g, int eta, int max_w, const int* kind, const int* jj,
+                                 const int* kk, const int* lo, const int* w, const long long* poff, float* psip,
+                                 hipStream_t s) {
+  const long long n = (long long)max_w * g.M;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_one_sided_pack, dim3((unsigned)((n + 255) / 256), (unsigned)eta), dim3(256), 0, s, g, kind,
+                     jj, kk, lo, w, poff, psip);
+  return hipGetLastError();
+}
+
+hipError_t launch_one_sided_expand(const float* psip, int M, int N, int eta, const int* lo, const int* w,
+                                   const long long* poff, float* out, hipStream_t s) {
+  const long long n = (long long)M * N;
+  hipLaunchKernelGGL(k_one_sided_expand, dim3((unsigned)((n + 255) / 256), (unsigned)eta), dim3(256), 0, s, psip, M,
+                     N, lo, w, poff, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_spectra(const GenParams& g, int eta, const int* kind, const int* jj, const int* kk,
                           float* psi, hipStream_t s) {

@@ -33,40 +33,10 @@
 // DFT of the Hermitian row.
 #include "fft_core.hpp"
 #include "internal.hpp"
+#include "launch_cfg.hpp"
 
 namespace ffst {
 namespace {
-
-__host__ __device__ constexpr int line_values(int L) { return L >= 16 ? 16 : L; }
-// Column lines: 8 values per lane up to length 1024 (8*8*8 needs the same
-// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above.
-__host__ __device__ constexpr int col_values(int L) { return L > 1024 ? 16 : (L >= 8 ? 8 : L); }
-// LDS stride per line/row: congruent to 17 mod 32, so that 16 lanes reading
-// the same column of 16 rows, and 16 lanes reading 16 consecutive values of
-// one row, both touch distinct banks.
-__host__ __device__ constexpr int lds_stride(int L, int V) { return stride_mod32(lds_group_len(L, V), 17); }
-
-// Rows of length N = 2L, RB rows per block.
-template <int L>
-struct RowCfg {
-  static constexpr int V = line_values(L);
-  static constexpr int G = L / V;                      // lanes per row
-  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 8;
-  static constexpr int THREADS = RB * G;
-  static constexpr int STRIDE = lds_stride(L, V);
-};
-
-// Contiguous lines of length L (the column direction, L = M).
-template <int L>
-struct LineCfg {
-  static constexpr int V = col_values(L);
-  static constexpr int G = L / V;
-  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
-  static constexpr int LPB = THREADS / G;             // lines per block
-  static constexpr int STRIDE = lds_stride(L, V);
-};
 
 // ---------------------------------------------------------------- rows
 
@@ -81,20 +51,6 @@ struct RowJob {
   Windows win;
   const float2* twN;        // exp(-2 pi i m / N), m < N
 };
-
-struct RowUnit {
-  int img, plane, r0;
-};
-
-__device__ __forceinline__ RowUnit row_unit(int u, int blocks_per_plane, int nplanes, float inv_nplanes, int rb,
-                                            int plane0) {
-  RowUnit ru;
-  const int pq = u / blocks_per_plane;
-  ru.r0 = (u - pq * blocks_per_plane) * rb;
-  ru.img = (int)(((float)pq + 0.5f) * inv_nplanes);  // exact for pq < 2^20
-  ru.plane = plane0 + pq - ru.img * nplanes;
-  return ru;
-}
 
 // SMALL: images with fewer than RB rows; the block then covers job.rb rows.
 //
@@ -494,26 +450,6 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_wide(AdjLineJ
 // Row kernels take the complex length L = N/2, line kernels the length M.
 #define FFST_ROW_CASES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048)
 #define FFST_COL_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-
-int g_num_cus = 0;
-
-int num_cus() {
-  if (g_num_cus == 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      g_num_cus = prop.multiProcessorCount;
-    if (g_num_cus <= 0) g_num_cus = 256;
-  }
-  return g_num_cus;
-}
-
-// Persistent grids: enough blocks for the work, at most `per_cu` per CU.
-int grid_for(long long units, int threads) {
-  const int per_cu = threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8);
-  const long long cap = (long long)num_cus() * per_cu;
-  return (int)(units < cap ? (units > 0 ? units : 1) : cap);
-}
 
 }  // namespace
 

@@ -12,21 +12,25 @@ class Plan:
 
     forward(x):  x (M, N) or (B, M, N) float32 -> (eta, M, N) or (B, eta, M, N)
     adjoint(c):  the reverse shapes; inverse(c) is the same computation.
+    With complex_shearlets=True (one-sided spectra) the coefficients are
+    complex64 and adjoint(c) returns the real image Re sum_i ... .
     Calls are asynchronous on torch's current stream of the plan's device.
     One workspace per batch size is cached on the plan, so calls that may
     run at the same time on different streams need their own `ws`.
     """
 
-    def __init__(self, M, N, J=0, max_scale="max", shearlet="meyer", device=None):
+    def __init__(self, M, N, J=0, max_scale="max", shearlet="meyer", complex_shearlets=False, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1202_1773_amd needs a ROCm GPU (no CPU path exists)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = None
         with torch.cuda.device(self.device):
-            self._h = _lib.ffst_spectra(M, N, J, max_scale, _SHEARLETS[shearlet])
+            self._h = _lib.ffst_spectra(M, N, J, max_scale, _SHEARLETS[shearlet], complex_shearlets)
         self.M, self.N, self.J, self.eta = _lib.ffst_plan_info(self._h)
         self.max_scale = max_scale
         self.shearlet = shearlet
+        self.complex_shearlets = bool(complex_shearlets)
+        self.coef_dtype = torch.complex64 if self.complex_shearlets else torch.float32
         self._ws = {}
 
     # ---------------------------------------------------------------- memory
@@ -45,9 +49,9 @@ class Plan:
     def _stream(self):
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def _check(self, t, trailing):
-        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float32:
-            raise ValueError(f"expected a float32 tensor on {self.device}")
+    def _check(self, t, trailing, dtype=torch.float32):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != dtype:
+            raise ValueError(f"expected a {dtype} tensor on {self.device}")
         if not t.is_contiguous():
             raise ValueError("expected a contiguous tensor")
         if tuple(t.shape[-len(trailing):]) != trailing:
@@ -60,16 +64,16 @@ class Plan:
         xb = x.reshape(-1, self.M, self.N)
         B = xb.shape[0]
         if out is None:
-            out = torch.empty((B, self.eta, self.M, self.N), dtype=torch.float32, device=self.device)
-        self._check(out, (self.eta, self.M, self.N))
+            out = torch.empty((B, self.eta, self.M, self.N), dtype=self.coef_dtype, device=self.device)
+        self._check(out, (self.eta, self.M, self.N), self.coef_dtype)
         if out.numel() != B * self.eta * self.M * self.N:
             raise ValueError("output has the wrong number of elements")
-        _lib.ffst_forward(self._h, xb.data_ptr(), out.data_ptr(), B,
-                          ws if ws is not None else self.workspace(B), self._stream())
+        call = _lib.ffst_forward_complex if self.complex_shearlets else _lib.ffst_forward
+        call(self._h, xb.data_ptr(), out.data_ptr(), B, ws if ws is not None else self.workspace(B), self._stream())
         return out.reshape(self.eta, self.M, self.N) if single else out.reshape(B, self.eta, self.M, self.N)
 
     def adjoint(self, c, out=None, ws=None):
-        self._check(c, (self.eta, self.M, self.N))
+        self._check(c, (self.eta, self.M, self.N), self.coef_dtype)
         single = c.dim() == 3
         cb = c.reshape(-1, self.eta, self.M, self.N)
         B = cb.shape[0]
@@ -78,8 +82,8 @@ class Plan:
         self._check(out, (self.M, self.N))
         if out.numel() != B * self.M * self.N:
             raise ValueError("output has the wrong number of elements")
-        _lib.ffst_adjoint(self._h, cb.data_ptr(), out.data_ptr(), B,
-                          ws if ws is not None else self.workspace(B), self._stream())
+        call = _lib.ffst_adjoint_complex if self.complex_shearlets else _lib.ffst_adjoint
+        call(self._h, cb.data_ptr(), out.data_ptr(), B, ws if ws is not None else self.workspace(B), self._stream())
         return out.reshape(self.M, self.N) if single else out.reshape(B, self.M, self.N)
 
     def inverse(self, c, out=None, ws=None):
@@ -87,7 +91,8 @@ class Plan:
 
     # --------------------------------------------------------------- helpers
     def spectra(self, full_plane=False):
-        """The plan's float32 spectra, (eta, M, N/2+1) or (eta, M, N)."""
+        """The plan's float32 spectra, (eta, M, N/2+1) or (eta, M, N); the
+        one-sided spectra of a complex plan exist on the full plane only."""
         cols = self.N if full_plane else self.N // 2 + 1
         dst = torch.empty((self.eta, self.M, cols), dtype=torch.float32, device=self.device)
         torch.cuda.synchronize(self.device)
@@ -95,7 +100,8 @@ class Plan:
         return dst
 
     def windows(self):
-        """Per spectrum, the first and last half-plane column holding a nonzero."""
+        """Per spectrum, the first and last column holding a nonzero (half
+        plane; for a complex plan a cyclic range of full-plane columns)."""
         return _lib.ffst_plan_windows(self._h, self.eta)
 
     def close(self):

@@ -52,6 +52,9 @@ def test_spectra_rejects_bad_arguments(lib):
     assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
     bad = _lib.ffst_options(0, 7)
     assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
+    bad = _lib.ffst_options(0, 0, 2)
+    assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
+    assert "complex_shearlets" in _lib.ffst_last_error()
 
 
 def test_calls_reject_bad_plans(lib):
@@ -61,6 +64,9 @@ def test_calls_reject_bad_plans(lib):
     assert lib.ffst_forward(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_adjoint(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_inverse(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_forward_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_adjoint_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_inverse_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_get_spectra(None, None, 0) == _lib.FFST_EBADPLAN
     assert lib.ffst_plan_windows(None, None, None) == _lib.FFST_EBADPLAN
     assert "plan" in _lib.ffst_last_error()
@@ -72,6 +78,7 @@ def test_profiling_table(lib):
     assert n >= 9
     names = [_lib.ffst_kernel_name(i) for i in range(n)]
     assert "k_fwd_cols" in names and "k_adj_cols" in names
+    assert "k_fwd_cols(complex)" in names and "k_adj_cols(complex)" in names
     assert lib.ffst_kernel_name(n) == b""
     with pytest.raises(_lib.FfstError):
         _lib.ffst_profile_read(n)
