@@ -85,6 +85,15 @@ typedef struct {
                             whose DFT mirror lies on the same side. The
                             coefficients are complex; such a plan is used with
                             the *_complex transform calls only. */
+    int aux_order;       /* auxiliary function v behind every window (Remark on
+                            the construction of v): 0 = eq. (v), the default
+                            (v'(x) = -140 x^3 (x-1)^3, shearlets in C^3);
+                            k in 1 .. 10: v'(x) = c x^k (x-1)^k with v(1) = 1
+                            (C^k); -1: the C-infinity function
+                            s(x-1) / (s(x-1) + s(x)),
+                            s(x) = exp(-(1/(1+x)^2 + 1/(1-x)^2)). Every choice
+                            keeps v(x) + v(1-x) = 1, so the frame stays
+                            Parseval. */
 } ffst_options;
 
 /*

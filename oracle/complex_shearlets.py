@@ -44,9 +44,9 @@ def orientation(kind, j, k):
     return (t, 1.0) if kind == "v" else (1.0, t)
 
 
-def one_sided_plane(M, N, J, i, max_scale="max", shearlet="meyer"):
+def one_sided_plane(M, N, J, i, max_scale="max", shearlet="meyer", aux=3):
     """Psi+_i on the (M, N) grid, float64, natural DFT order."""
-    psi = spectrum_plane(M, N, J, i, max_scale, True, shearlet)
+    psi = spectrum_plane(M, N, J, i, max_scale, True, shearlet, aux)
     kind, j, k = index_table(J)[i]
     d = orientation(kind, j, k)
     if d is None:
@@ -58,9 +58,9 @@ def one_sided_plane(M, N, J, i, max_scale="max", shearlet="meyer"):
     return np.where(split, np.where(side > 0, np.sqrt(2.0) * psi, 0.0), psi)
 
 
-def one_sided_spectra(M, N, J, max_scale="max", shearlet="meyer"):
+def one_sided_spectra(M, N, J, max_scale="max", shearlet="meyer", aux=3):
     eta = len(index_table(J))
-    return np.stack([one_sided_plane(M, N, J, i, max_scale, shearlet) for i in range(eta)])
+    return np.stack([one_sided_plane(M, N, J, i, max_scale, shearlet, aux) for i in range(eta)])
 
 
 def forward(f, psi_plus):

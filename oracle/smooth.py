@@ -22,14 +22,14 @@ import numpy as np
 from .windows import psi2, varphi
 
 
-def tensor_lowpass(w1, w2):
+def tensor_lowpass(w1, w2, aux=3):
     """Phi(w) = varphi(w1) varphi(w2), eq. (Phi)."""
-    return varphi(w1) * varphi(w2)
+    return varphi(w1, aux) * varphi(w2, aux)
 
 
-def corona(w1, w2):
+def corona(w1, w2, aux=3):
     """Psi1(w) = sqrt(Phi^2(w / 4) - Phi^2(w)), eq. (newPsi1)."""
-    d = tensor_lowpass(w1 / 4.0, w2 / 4.0) ** 2 - tensor_lowpass(w1, w2) ** 2
+    d = tensor_lowpass(w1 / 4.0, w2 / 4.0, aux) ** 2 - tensor_lowpass(w1, w2, aux) ** 2
     return np.sqrt(np.maximum(d, 0.0))
 
 
@@ -39,14 +39,14 @@ def _ratio(num, den):
     return out
 
 
-def smooth_spectrum(kind, j, k, w1, w2):
+def smooth_spectrum(kind, j, k, w1, w2, aux=3):
     """One smooth spectrum on the grid (before the Nyquist fix)."""
     a1, a2 = np.abs(w1), np.abs(w2)
     if kind == "lowpass":
-        return tensor_lowpass(w1, w2)
-    radial = corona(w1 / 4.0 ** j, w2 / 4.0 ** j)
-    horiz = radial * psi2(2.0 ** j * _ratio(w2, w1) + k)
-    vert = radial * psi2(2.0 ** j * _ratio(w1, w2) + k)
+        return tensor_lowpass(w1, w2, aux)
+    radial = corona(w1 / 4.0 ** j, w2 / 4.0 ** j, aux)
+    horiz = radial * psi2(2.0 ** j * _ratio(w2, w1) + k, aux)
+    vert = radial * psi2(2.0 ** j * _ratio(w1, w2) + k, aux)
     if kind == "h":
         return np.where(a2 < a1, horiz, 0.0)
     if kind == "v":

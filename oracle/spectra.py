@@ -65,30 +65,30 @@ def _ratio(num, den):
     return out
 
 
-def horizontal_formula(j, k, w1, w2):
+def horizontal_formula(j, k, w1, w2, aux=3):
     """psi1(4^-j w1) psi2(2^j w2 / w1 + k), the dilated and sheared shearlet of
     Sec. 3.1 (without the cone cut-off)."""
-    return psi1(w1 / 4.0 ** j) * psi2(2.0 ** j * _ratio(w2, w1) + k)
+    return psi1(w1 / 4.0 ** j, aux) * psi2(2.0 ** j * _ratio(w2, w1) + k, aux)
 
 
-def vertical_formula(j, k, w1, w2):
+def vertical_formula(j, k, w1, w2, aux=3):
     """Same with the roles of w1 and w2 interchanged (eq. verticalShearlet)."""
-    return psi1(w2 / 4.0 ** j) * psi2(2.0 ** j * _ratio(w1, w2) + k)
+    return psi1(w2 / 4.0 ** j, aux) * psi2(2.0 ** j * _ratio(w1, w2) + k, aux)
 
 
-def spectrum(kind, j, k, w1, w2):
+def spectrum(kind, j, k, w1, w2, aux=3):
     """One spectrum Psi_i on the grid (w1, w2), before the Nyquist fix."""
     a1, a2 = np.abs(w1), np.abs(w2)
     if kind == "lowpass":
-        return np.where(a2 <= a1, varphi(w1), varphi(w2))
+        return np.where(a2 <= a1, varphi(w1, aux), varphi(w2, aux))
     if kind == "h":
-        return np.where(a2 < a1, horizontal_formula(j, k, w1, w2), 0.0)
+        return np.where(a2 < a1, horizontal_formula(j, k, w1, w2, aux), 0.0)
     if kind == "v":
-        return np.where(a1 < a2, vertical_formula(j, k, w1, w2), 0.0)
+        return np.where(a1 < a2, vertical_formula(j, k, w1, w2, aux), 0.0)
     if kind == "hv":
         horiz_and_seam_line = (a2 <= a1) & (a1 > 0)
-        out = np.where(horiz_and_seam_line, horizontal_formula(j, k, w1, w2), 0.0)
-        return np.where(a1 < a2, vertical_formula(j, k, w1, w2), out)
+        out = np.where(horiz_and_seam_line, horizontal_formula(j, k, w1, w2, aux), 0.0)
+        return np.where(a1 < a2, vertical_formula(j, k, w1, w2, aux), out)
     raise ValueError(kind)
 
 
@@ -124,27 +124,28 @@ def symmetrize_line(line):
     return np.sqrt((line * line + line[..., partner] ** 2) / 2.0)
 
 
-def spectrum_plane(M, N, J, i, max_scale="max", real_real=True, shearlet="meyer"):
-    """Plane i of the spectra stack, float64 (M, N), natural DFT order."""
+def spectrum_plane(M, N, J, i, max_scale="max", real_real=True, shearlet="meyer", aux=3):
+    """Plane i of the spectra stack, float64 (M, N), natural DFT order; `aux`
+    selects the auxiliary function v (see oracle.windows)."""
     w1, w2 = frequencies(M, N, J, max_scale)
     kind, j, k = index_table(J)[i]
     if shearlet == "meyer":
-        plane = spectrum(kind, j, k, w1, w2)
+        plane = spectrum(kind, j, k, w1, w2, aux)
     elif shearlet == "smooth":
         from .smooth import smooth_spectrum
-        plane = smooth_spectrum(kind, j, k, w1, w2)
+        plane = smooth_spectrum(kind, j, k, w1, w2, aux)
     else:
         raise ValueError(shearlet)
     return symmetrize_nyquist(plane) if real_real else plane
 
 
-def spectra(M, N, J=None, max_scale="max", real_real=True, shearlet="meyer"):
+def spectra(M, N, J=None, max_scale="max", real_real=True, shearlet="meyer", aux=3):
     """All eta spectra as a float64 (eta, M, N) stack."""
     if J is None:
         J = default_scales(M, N)
     if J < 1:
         raise ValueError("need at least one scale")
     return np.stack([
-        spectrum_plane(M, N, J, i, max_scale, real_real, shearlet)
+        spectrum_plane(M, N, J, i, max_scale, real_real, shearlet, aux)
         for i in range(num_spectra(J))
     ])

@@ -36,7 +36,7 @@ class FfstError(RuntimeError):
 
 class ffst_options(ctypes.Structure):
     _fields_ = [("max_scale_min", ctypes.c_int), ("shearlet", ctypes.c_int),
-                ("complex_shearlets", ctypes.c_int)]
+                ("complex_shearlets", ctypes.c_int), ("aux_order", ctypes.c_int)]
 
 
 _lib = None
@@ -90,11 +90,22 @@ def _check(status, where):
 
 # ---- thin wrappers with the C names ------------------------------------
 
-def ffst_spectra(M, N, J=0, max_scale="max", shearlet=FFST_SHEARLET_MEYER, complex_shearlets=False):
+def aux_order(aux):
+    """C value of the auxiliary-function choice: 3 -> 0 (eq. (v), the default),
+    k -> k, "inf" -> -1."""
+    if aux == "inf":
+        return -1
+    if isinstance(aux, int) and 1 <= aux <= 10:
+        return 0 if aux == 3 else aux
+    raise ValueError("aux must be an int in [1, 10] or 'inf'")
+
+
+def ffst_spectra(M, N, J=0, max_scale="max", shearlet=FFST_SHEARLET_MEYER, complex_shearlets=False, aux=3):
     """Create a plan and generate its spectra; returns the opaque handle."""
     lib = load()
     out = ctypes.c_void_p()
-    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet), 1 if complex_shearlets else 0)
+    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet), 1 if complex_shearlets else 0,
+                       aux_order(aux))
     _check(lib.ffst_spectra_ex(int(M), int(N), int(J), ctypes.byref(opt), ctypes.byref(out)), "ffst_spectra")
     return out.value
 

@@ -356,6 +356,8 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     return fail(FFST_EINVAL, "unknown shearlet %d", o.shearlet);
   if (o.complex_shearlets != 0 && o.complex_shearlets != 1)
     return fail(FFST_EINVAL, "complex_shearlets must be 0 or 1");
+  if (o.aux_order < -1 || o.aux_order > 10)
+    return fail(FFST_EINVAL, "aux_order must be -1 (C-infinity), 0 (default) or 1 .. 10 (got %d)", o.aux_order);
   if (J <= 0) J = default_scales(M, N);
   if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
   if (!is_pow2(M) || !is_pow2(N) || M < 8 || N < 8 || M > 4096 || N > 4096 || !supported_length(M))
@@ -404,7 +406,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
-  GenParams g{M, N, p->delta, o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? 1 : 0};
+  GenParams g{M, N, p->delta, o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? 1 : 0, o.aux_order == 0 ? 3 : o.aux_order};
   const bool cplx = o.complex_shearlets == 1;
   e = timed(KID_SPECTRA, nullptr, [&] { return launch_spectra(g, p->eta, d_kind, d_j, d_k, p->psi, nullptr); });
   if (e == hipSuccess && !cplx)

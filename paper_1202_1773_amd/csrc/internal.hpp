@@ -13,6 +13,7 @@ struct GenParams {
   int M, N;
   double delta;       // grid spacing (Sec. 3.5.1)
   int smooth;         // 0: Meyer shearlets, 1: smooth shearlets of Sec. 3.4
+  int aux;            // auxiliary function v: 3 = eq. (v), k >= 1 = C^k, -1 = C-infinity
 };
 
 // Per-plane nonzero column window [lo, lo + w) of the half plane and the

@@ -8,6 +8,8 @@
 //
 // Windows (Sec. 2.1, 2.4, 3.4):
 //   v(x)      = x^4 (35 - 84 x + 70 x^2 - 20 x^3) on [0, 1], clamped outside
+//               (or one of the other choices of the Remark on the construction
+//               of v: C^k polynomials, C-infinity)
 //   psi1(w)   = 0 | sin(pi/2 v(2|w|-1)) | 1 | cos(pi/2 v(|w|/2-1)) | 0 on the
 //               breakpoints 1/2, 1, 2, 4 (the closed form of Sec. 3.4)
 //   psi2(w)   = sqrt(v(1 - |w|))
@@ -30,57 +32,82 @@
 namespace ffst {
 namespace {
 
-__device__ double v_aux(double x) {
+// Auxiliary function v on [0, 1], clamped outside. aux = 3: eq. (v) by
+// Horner; aux = k >= 1: the C^k choice v'(x) = c x^k (x-1)^k, v(1) = 1, i.e.
+// the binomial tail sum_{m=k+1}^{2k+1} C(2k+1, m) x^m (1-x)^(2k+1-m) (every
+// term nonnegative), summed upward with the ratio of consecutive terms;
+// aux < 0: the C-infinity choice s(x-1) / (s(x-1) + s(x)) of the Remark on
+// the construction of v, written as 1 / (1 + s(x) / s(x-1)) so that neither
+// exponential underflows into 0/0.
+__device__ double v_aux(double x, int aux) {
   if (x <= 0.0) return 0.0;
   if (x >= 1.0) return 1.0;
-  const double x2 = x * x;
-  return x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+  if (aux == 3) {
+    const double x2 = x * x;
+    return x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+  }
+  if (aux < 0) {
+    const double e_lo = 1.0 / (x * x) + 1.0 / ((2.0 - x) * (2.0 - x));          // -log s(x - 1)
+    const double e_hi = 1.0 / ((1.0 + x) * (1.0 + x)) + 1.0 / ((1.0 - x) * (1.0 - x));  // -log s(x)
+    return 1.0 / (1.0 + exp(e_lo - e_hi));
+  }
+  const int n = 2 * aux + 1;
+  const double y = 1.0 - x;
+  double binom = 1.0;                      // C(n, k + 1)
+  for (int m = 1; m <= aux + 1; ++m) binom = binom * (double)(n - m + 1) / (double)m;
+  double term = binom * pow(x, (double)(aux + 1)) * pow(y, (double)aux);
+  double sum = 0.0;
+  for (int m = aux + 1; m <= n; ++m) {
+    sum += term;
+    term *= (double)(n - m) / (double)(m + 1) * (x / y);
+  }
+  return sum;
 }
 
-__device__ double psi1_hat(double w) {
+__device__ double psi1_hat(double w, int aux) {
   const double a = fabs(w);
   if (a <= 0.5) return 0.0;
-  if (a < 1.0) return sin(M_PI_2 * v_aux(2.0 * a - 1.0));
+  if (a < 1.0) return sin(M_PI_2 * v_aux(2.0 * a - 1.0, aux));
   if (a <= 2.0) return 1.0;
-  if (a < 4.0) return cos(M_PI_2 * v_aux(0.5 * a - 1.0));
+  if (a < 4.0) return cos(M_PI_2 * v_aux(0.5 * a - 1.0, aux));
   return 0.0;
 }
 
-__device__ double psi2_hat(double w) { return sqrt(v_aux(1.0 - fabs(w))); }
+__device__ double psi2_hat(double w, int aux) { return sqrt(v_aux(1.0 - fabs(w), aux)); }
 
-__device__ double varphi(double w) {
+__device__ double varphi(double w, int aux) {
   const double a = fabs(w);
   if (a <= 0.5) return 1.0;
-  if (a < 1.0) return cos(M_PI_2 * v_aux(2.0 * a - 1.0));
+  if (a < 1.0) return cos(M_PI_2 * v_aux(2.0 * a - 1.0, aux));
   return 0.0;
 }
 
 // Smooth corona function of Sec. 3.4 at the dilated point 4^-j w.
-__device__ double corona(double w1, double w2, double dil) {
+__device__ double corona(double w1, double w2, double dil, int aux) {
   const double a1 = w1 * dil, a2 = w2 * dil;
-  const double outer = varphi(0.25 * a1) * varphi(0.25 * a2);
-  const double inner = varphi(a1) * varphi(a2);
+  const double outer = varphi(0.25 * a1, aux) * varphi(0.25 * a2, aux);
+  const double inner = varphi(a1, aux) * varphi(a2, aux);
   const double d = outer * outer - inner * inner;
   return d > 0.0 ? sqrt(d) : 0.0;
 }
 
-__device__ double spectrum_value(int kind, int j, int k, int smooth, double w1, double w2) {
+__device__ double spectrum_value(int kind, int j, int k, int smooth, int aux, double w1, double w2) {
   const double a1 = fabs(w1), a2 = fabs(w2);
   if (kind == KIND_LOWPASS) {
-    if (smooth) return varphi(w1) * varphi(w2);
-    return a2 <= a1 ? varphi(w1) : varphi(w2);
+    if (smooth) return varphi(w1, aux) * varphi(w2, aux);
+    return a2 <= a1 ? varphi(w1, aux) : varphi(w2, aux);
   }
   const double dil = ldexp(1.0, -2 * j);   // 4^-j
   const double shr = ldexp(1.0, j);        // 2^j
   const bool use_v = (kind == KIND_V) ? (a1 < a2) : (kind == KIND_SEAM && a1 < a2);
   const bool use_h = (kind == KIND_H) ? (a2 < a1) : (kind == KIND_SEAM && !(a1 < a2) && a1 > 0.0);
   if (use_h) {
-    const double radial = smooth ? corona(w1, w2, dil) : psi1_hat(w1 * dil);
-    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w2 / w1) + k);
+    const double radial = smooth ? corona(w1, w2, dil, aux) : psi1_hat(w1 * dil, aux);
+    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w2 / w1) + k, aux);
   }
   if (use_v) {
-    const double radial = smooth ? corona(w1, w2, dil) : psi1_hat(w2 * dil);
-    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w1 / w2) + k);
+    const double radial = smooth ? corona(w1, w2, dil, aux) : psi1_hat(w2 * dil, aux);
+    return radial == 0.0 ? 0.0 : radial * psi2_hat(shr * (w1 / w2) + k, aux);
   }
   return 0.0;
 }
@@ -90,7 +117,7 @@ __device__ __forceinline__ int signed_freq(int p, int D) { return p <= (D + 1) /
 __device__ double grid_value(const GenParams& g, int kind, int j, int k, int r, int c) {
   const double w1 = g.delta * signed_freq(c, g.N);
   const double w2 = g.delta * signed_freq(r, g.M);
-  return spectrum_value(kind, j, k, g.smooth, w1, w2);
+  return spectrum_value(kind, j, k, g.smooth, g.aux, w1, w2);
 }
 
 // Grid value with the real-coefficient fix of Sec. 3.8.1, at any point

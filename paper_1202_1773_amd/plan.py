@@ -14,22 +14,26 @@ class Plan:
     adjoint(c):  the reverse shapes; inverse(c) is the same computation.
     With complex_shearlets=True (one-sided spectra) the coefficients are
     complex64 and adjoint(c) returns the real image Re sum_i ... .
+    aux picks the auxiliary function v behind the windows: 3 (eq. (v), the
+    default), another order k in [1, 10] (C^k) or "inf" (C-infinity).
     Calls are asynchronous on torch's current stream of the plan's device.
     One workspace per batch size is cached on the plan, so calls that may
     run at the same time on different streams need their own `ws`.
     """
 
-    def __init__(self, M, N, J=0, max_scale="max", shearlet="meyer", complex_shearlets=False, device=None):
+    def __init__(self, M, N, J=0, max_scale="max", shearlet="meyer", complex_shearlets=False, aux=3,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1202_1773_amd needs a ROCm GPU (no CPU path exists)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = None
         with torch.cuda.device(self.device):
-            self._h = _lib.ffst_spectra(M, N, J, max_scale, _SHEARLETS[shearlet], complex_shearlets)
+            self._h = _lib.ffst_spectra(M, N, J, max_scale, _SHEARLETS[shearlet], complex_shearlets, aux)
         self.M, self.N, self.J, self.eta = _lib.ffst_plan_info(self._h)
         self.max_scale = max_scale
         self.shearlet = shearlet
         self.complex_shearlets = bool(complex_shearlets)
+        self.aux = aux
         self.coef_dtype = torch.complex64 if self.complex_shearlets else torch.float32
         self._ws = {}
 

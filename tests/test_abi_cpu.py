@@ -55,6 +55,13 @@ def test_spectra_rejects_bad_arguments(lib):
     bad = _lib.ffst_options(0, 0, 2)
     assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
     assert "complex_shearlets" in _lib.ffst_last_error()
+    for order in (-2, 11):
+        bad = _lib.ffst_options(0, 0, 0, order)
+        assert lib.ffst_spectra_ex(64, 64, 2, ctypes.byref(bad), ctypes.byref(out)) == _lib.FFST_EINVAL
+        assert "aux_order" in _lib.ffst_last_error()
+    with pytest.raises(ValueError):
+        _lib.aux_order(0)
+    assert _lib.aux_order(3) == 0 and _lib.aux_order("inf") == -1 and _lib.aux_order(7) == 7
 
 
 def test_calls_reject_bad_plans(lib):
