@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gcoef/s fwd+adjoint @512² J=3 FP32 (%HBM roofline); batched vs plain"
-KERNEL_SOURCES = ["fft_core.hpp", "transform.hip", "spectra.hip", "internal.hpp", "api.hip"]
+KERNEL_SOURCES = ["fft_core.hpp", "launch_cfg.hpp", "internal.hpp", "spectra.hip", "transform_rows.hip",
+                  "transform_cols.hip", "complex.hip", "api.hip"]
 
 
 def source_hash():

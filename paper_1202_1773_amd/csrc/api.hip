@@ -122,7 +122,6 @@ void drain_profile() {
 
 // ---- plan construction -------------------------------------------------
 
-bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int default_scales(int M, int N) {
   int L = std::max(M, N), lg = 0;
@@ -360,8 +359,9 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     return fail(FFST_EINVAL, "aux_order must be -1 (C-infinity), 0 (default) or 1 .. 10 (got %d)", o.aux_order);
   if (J <= 0) J = default_scales(M, N);
   if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
-  if (!is_pow2(M) || !is_pow2(N) || M < 8 || N < 8 || M > 4096 || N > 4096 || !supported_length(M))
-    return fail(FFST_EUNSUPPORTED, "GPU path supports powers of two in [8, 4096] (got %d x %d)", M, N);
+  if (!supported_length(M) || !supported_length(N) || !supported_row_length(N))
+    return fail(FFST_EUNSUPPORTED,
+                "GPU path supports sides 2^k in [8, 4096] and 3 * 2^k in [12, 3072] (got %d x %d)", M, N);
 
   ffst_plan* p = new (std::nothrow) ffst_plan();
   if (!p) return fail(FFST_ENOMEM, "host allocation failed");

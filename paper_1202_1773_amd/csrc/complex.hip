@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_inv(CRowJob jo
   const int j = threadIdx.x % G;
   const int rb = job.rb;
   const int tr = threadIdx.x % rb;        // row (transpose phase)
-  const int tc = threadIdx.x / rb;        // first column (transpose phase)
+  // first column (transpose phase); threads beyond rb * (NT / rb) sit out
+  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
   const int cstep = NT / rb;
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_inv(CRowJob jo
 #pragma unroll
     for (int m = 0; m < V; ++m) {
       const int k = tc + cstep * m;
-      const int cm = (k - lo) & (L - 1);
+      const int cm = k >= lo ? k - lo : k - lo + L;
       dst[m] = (k < L && cm < w) ? in[(long long)cm * job.zp] : make_float2(0.f, 0.f);
     }
   };
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
   const int j = threadIdx.x % G;
   const int rb = job.rb;
   const int tr = threadIdx.x % rb;
-  const int tc = threadIdx.x / rb;
+  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
   const int cstep = NT / rb;
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
     const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
     float2* out = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
 #pragma unroll 4
-    for (int m = tc; m < w; m += cstep) out[(long long)m * job.zp] = zr[lpad<V>((lo + m) & (L - 1))];
+    for (int m = tc; m < w; m += cstep) out[(long long)m * job.zp] = zr[lpad<V>(wrap_once(lo + m, L))];
     __syncthreads();
   }
 }
@@ -183,14 +184,14 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob
     const int qq = q < total ? q : 0;
     const int img = qq / job.nlines;
     const int2 ln = job.lines[qq % job.nlines];
-    const int c = (job.win.lo[ln.x] + ln.y) & (job.N - 1);
+    const int c = wrap_once(job.win.lo[ln.x] + ln.y, job.N);
     const bool upper = c > job.N / 2;
     const float2* fb = job.F + ((long long)img * job.H + (upper ? job.N - c : c)) * job.pitch;
     const float* pb = job.psip + job.poff[ln.x] + (long long)ln.y * M;
 #pragma unroll
     for (int s = 0; s < V; ++s) {
       const int r = j + G * s;
-      const float2 fv = fb[upper ? ((M - r) & (M - 1)) : r];
+      const float2 fv = fb[upper ? mirror_index(r, M) : r];
       fn[s] = upper ? conjf2(fv) : fv;
       pn[s] = pb[r];
     }
@@ -300,7 +301,7 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
     lds_sync<C::SYNC>();
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      const float2 rv = my[lpad<V>((M - (j + G * s)) & (M - 1))];
+      const float2 rv = my[lpad<V>(mirror_index(j + G * s, M))];
       acc1[s] = cscale(cadd(acc1[s], conjf2(rv)), job.scale);
     }
     lds_sync<C::SYNC>();
@@ -329,8 +330,10 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_c(CAdjLineJob
 }
 
 // Complex row kernels take the full length N, line kernels the length M.
-#define FFST_CROW_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-#define FFST_CCOL_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+// Powers of two and 3 * 2^k.
+#define FFST_CROW_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
+  X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
+#define FFST_CCOL_CASES(X) FFST_CROW_CASES(X)
 
 CRowJob make_crow_job(const CRowArgs& a, int rb_max) {
   CRowJob j;
@@ -343,7 +346,7 @@ CRowJob make_crow_job(const CRowArgs& a, int rb_max) {
   j.nplanes = a.nplanes;
   j.plane0 = a.plane0;
   j.M = a.M;
-  j.rb = a.M < rb_max ? a.M : rb_max;
+  j.rb = rows_per_block(a.M, rb_max);
   j.zp = a.zp;
   j.inv_nplanes = 1.0f / (float)a.nplanes;
   j.win = a.win;

@@ -5,8 +5,10 @@
 // s (s = 0 .. V-1). That layout is the same before and after the transform,
 // so a group loads and stores with unit stride across lanes.
 //
-// Each stage is a radix-R Stockham autosort step (R = V, and one final
-// smaller radix when L is not a power of V). A lane runs V/R butterflies per
+// Each stage is a radix-R Stockham autosort step, R being the largest
+// divisor of V that divides what is left of L (V, V, ..., then a smaller
+// power of two; with V = 12 for lengths 3 * 2^k: 12, 4, ..., 4, 2). A lane
+// runs V/R butterflies per
 // stage; butterfly b reads elements b + t*L/R, multiplies them by the twiddles
 // W_{pR}^{t (b mod p)} (p = product of the earlier radices), applies the
 // R-point DFT in registers and writes element (b/p)*p*R + (b mod p) + t*p.
@@ -66,6 +68,9 @@ __device__ __forceinline__ float2 rot135(float2 a) {
 template <int R, bool INV>
 struct Dft;
 
+// sin(pi/3), cos(pi/6)
+constexpr float kSin60 = 0.86602540378443864676f;
+
 template <bool INV>
 struct Dft<1, INV> {
   static __device__ __forceinline__ void run(float2*) {}
@@ -77,6 +82,20 @@ struct Dft<2, INV> {
     float2 t = a[0];
     a[0] = cadd(t, a[1]);
     a[1] = csub(t, a[1]);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    // y1,2 = a0 - (a1 + a2)/2 -+ i sin(2 pi/3) (a1 - a2) (forward sign)
+    const float2 t = cadd(a[1], a[2]);
+    const float2 m = make_float2(a[0].x - 0.5f * t.x, a[0].y - 0.5f * t.y);
+    const float2 d = csub(a[1], a[2]);
+    const float2 s = rot90<INV>(make_float2(kSin60 * d.x, kSin60 * d.y));
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(m, s);
+    a[2] = csub(m, s);
   }
 };
 
@@ -140,17 +159,72 @@ struct Dft<16, INV> {
   }
 };
 
+// 6 = 2 x 3: DFT3 of the even and the odd elements, twiddles exp(-+ 2 pi i k / 6).
+template <bool INV>
+struct Dft<6, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 e[3] = {a[0], a[2], a[4]};
+    float2 o[3] = {a[1], a[3], a[5]};
+    Dft<3, INV>::run(e);
+    Dft<3, INV>::run(o);
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    o[1] = cmul(o[1], make_float2(0.5f, sg * kSin60));
+    o[2] = cmul(o[2], make_float2(-0.5f, sg * kSin60));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] = cadd(e[k], o[k]);
+      a[k + 3] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// 12 = 2 x 6, twiddles exp(-+ 2 pi i k / 12).
+template <bool INV>
+struct Dft<12, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 e[6], o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      e[k] = a[2 * k];
+      o[k] = a[2 * k + 1];
+    }
+    Dft<6, INV>::run(e);
+    Dft<6, INV>::run(o);
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    o[1] = cmul(o[1], make_float2(kSin60, sg * 0.5f));
+    o[2] = cmul(o[2], make_float2(0.5f, sg * kSin60));
+    o[3] = rot90<INV>(o[3]);
+    o[4] = cmul(o[4], make_float2(-0.5f, sg * kSin60));
+    o[5] = cmul(o[5], make_float2(-kSin60, sg * 0.5f));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      a[k] = cadd(e[k], o[k]);
+      a[k + 6] = csub(e[k], o[k]);
+    }
+  }
+};
+
 // ----------------------------------------------------------- radix plan
 
-// Radices for length L with V values per lane: V, V, ..., then L / V^n.
+// Largest divisor of V that divides n.
+__host__ __device__ constexpr int largest_common_radix(int V, int n) {
+  int r = 1;
+  for (int d = 1; d <= V; ++d)
+    if (V % d == 0 && n % d == 0) r = d;
+  return r;
+}
+
+// Radices for length L with V values per lane: at each stage the largest
+// divisor of V that divides the remaining length (V, V, ..., then a smaller
+// one; every radix divides V).
 template <int L, int V>
 struct RadixPlan {
-  static_assert(L % V == 0 || L < V, "V must divide L");
+  static_assert(L % V == 0, "V must divide L");
   static constexpr int G = L / V;
   static constexpr int radix(int s) {
     int p = 1;
-    for (int i = 0; i < s; ++i) p *= ((L / p) % V == 0 ? V : L / p);
-    return (L / p) % V == 0 ? V : L / p;
+    for (int i = 0; i < s; ++i) p *= largest_common_radix(V, L / p);
+    return largest_common_radix(V, L / p);
   }
   static constexpr int span(int s) {  // product of the radices before stage s
     int p = 1;

@@ -168,6 +168,9 @@ struct CAdjLineArgs {
 };
 hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s);
 
-bool supported_length(int L);
+// Column lengths M and row lengths N the kernels are instantiated for:
+// powers of two in [8, 4096] and 3 * 2^k in [12, 3072].
+bool supported_length(int M);
+bool supported_row_length(int N);
 
 }  // namespace ffst

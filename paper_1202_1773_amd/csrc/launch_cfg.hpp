@@ -8,10 +8,31 @@
 
 namespace ffst {
 
-__host__ __device__ constexpr int line_values(int L) { return L >= 16 ? 16 : L; }
+// Values per lane. Lengths 3 * 2^k use 12 (radices 12, 4, ..., 2); powers
+// of two use 16 along rows.
+__host__ __device__ constexpr int line_values(int L) {
+  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L >= 16 ? 16 : L);
+}
 // Column lines: 8 values per lane up to length 1024 (8*8*8 needs the same
-// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above.
-__host__ __device__ constexpr int col_values(int L) { return L > 1024 ? 16 : (L >= 8 ? 8 : L); }
+// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above;
+// 12 for lengths 3 * 2^k.
+__host__ __device__ constexpr int col_values(int L) {
+  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L > 1024 ? 16 : (L >= 8 ? 8 : L));
+}
+
+// Rows per block that divide the image height: all M rows when M < rb_max,
+// else the largest divisor of M that divides rb_max (rb_max is a power of two).
+inline int rows_per_block(int M, int rb_max) {
+  if (M < rb_max) return M;
+  int rb = rb_max;
+  while (M % rb) rb /= 2;
+  return rb;
+}
+
+// Index helpers for lengths that need not be powers of two.
+__device__ __forceinline__ int wrap_once(int x, int L) { return x >= L ? x - L : x; }   // x in [0, 2L)
+__device__ __forceinline__ int mirror_index(int r, int L) { return r == 0 ? 0 : L - r; }  // -r mod L, r in [0, L)
+
 // LDS stride per line/row: congruent to 17 mod 32, so that 16 lanes reading
 // the same column of 16 rows, and 16 lanes reading 16 consecutive values of
 // one row, both touch distinct banks.

@@ -1,0 +1,328 @@
+// transform_cols.hip -- the column-direction passes of the FFST hot path on
+// gfx950: in-place line FFTs of the half-plane image spectra (k_line_fft),
+// the forward multiply + inverse column FFT per spectrum (k_fwd_lines) and
+// the adjoint's column FFT + multiply + sum over spectra (k_adj_lines). The
+// layouts and the order of the passes are described with the row kernels.
+#include "fft_core.hpp"
+#include "internal.hpp"
+#include "launch_cfg.hpp"
+
+namespace ffst {
+namespace {
+
+// In-place FFT of nlines contiguous lines of length M. Inverse with nparts > 0:
+// each line is first replaced by the sum of the same line of `nparts`
+// partial arrays (parts + p * part_stride), added in order p = 0, 1, ...
+template <int M, bool INV>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines, int pitch,
+                                                                  const float2* __restrict__ parts, int nparts,
+                                                                  long long part_stride,
+                                                                  const float2* __restrict__ twM) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, twM, 1);
+  for (int u = blockIdx.x; u * C::LPB < nlines; u += gridDim.x) {
+    const int line = u * C::LPB + g;
+    const bool ok = line < nlines;
+    float2* base = F + (long long)(ok ? line : 0) * pitch;
+    float2 v[V];
+    if (nparts > 0) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = make_float2(0.f, 0.f);
+      // up to 8 partial arrays, all loads issued before the (fixed-order) sums
+      constexpr int MAXP = 8;
+      float2 t[MAXP][V];
+#pragma unroll
+      for (int p = 0; p < MAXP; ++p) {
+        const float2* pb = parts + p * part_stride + (long long)(ok ? line : 0) * pitch;
+#pragma unroll
+        for (int s = 0; s < V; ++s) t[p][s] = p < nparts ? pb[j + G * s] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+        for (int s = 0; s < V; ++s) v[s] = cadd(v[s], t[p][s]);
+    } else {
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = base[j + G * s];
+    }
+    fft_group<M, V, INV, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
+    if (ok) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) base[j + G * s] = v[s];
+    }
+  }
+}
+
+struct FwdLineJob {
+  const float2* F;          // [nimg][H][M]
+  const float* psi;         // [eta][H][M]
+  const int2* lines;        // (spectrum, column) of the unit's lines
+  int nlines, nimg, H;
+  int pitch;                // complex elements between column lines of F and Y
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+
+// Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image).
+template <int M>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.nlines * job.nimg;
+  // software pipeline: the next unit's F and Psi lines are loaded while the
+  // current line is transformed
+  float2 fn[V];
+  float pn[V];
+  auto load_unit = [&](int u) {
+    const int q = u * C::LPB + g;
+    const int qq = q < total ? q : 0;
+    const int img = qq / job.nlines;
+    const int2 ln = job.lines[qq % job.nlines];
+    const float2* fb = job.F + ((long long)img * job.H + ln.y) * job.pitch;
+    const float* pb = job.psi + ((long long)ln.x * job.H + ln.y) * M;
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      fn[s] = fb[j + G * s];
+      pn[s] = pb[j + G * s];
+    }
+  };
+  int u = blockIdx.x;
+  if (u * C::LPB < total) load_unit(u);
+  for (; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int img = qq / job.nlines;          // lines of one image are ordered by column,
+    const int2 ln = job.lines[qq % job.nlines];  // so neighbouring lines share F[c]
+    const int i = ln.x, c = ln.y;
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = cscale(fn[s], pn[s] * job.scale);
+    if ((u + (int)gridDim.x) * C::LPB < total) load_unit(u + gridDim.x);
+    fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
+    if (ok) {
+      float2* yb = job.Y + img * job.y_img_stride + (job.win.off[i] - job.y_off_base) +
+                   (long long)(c - job.win.lo[i]) * job.pitch;
+#pragma unroll
+      for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
+    }
+  }
+}
+
+struct AdjLineJob {
+  const float2* Z;
+  long long z_img_stride, z_off_base;
+  Windows win;
+  const float* psi;
+  const int* col_ptr;       // CSR over columns -> spectra of this plane group
+  const int* col_planes;
+  int H, nimg, nparts;
+  int pitch;                // complex elements between column lines of Z, A and the partial sums
+  int accumulate;           // add to the existing partial sums
+  float2* out;              // FUSED: A [nimg][H][M]; else partial sums [nparts][nimg][H][M]
+  float scale;
+  const float2* twM;
+};
+
+// Line (img, c, part): sum_i Psi_i[c] * fft_col(Z_i[c - lo_i]) over the spectra
+// of column c (part p takes every nparts-th of them); FUSED: scale, inverse
+// FFT and store A[c].
+template <int M, bool FUSED>
+__device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
+  using C = LineCfg<M>;
+  constexpr int V = C::V, G = C::G;
+  __shared__ float2 lds[C::LPB * C::STRIDE];
+  const int g = threadIdx.x / G;
+  const int j = threadIdx.x % G;
+  float2* my = lds + g * C::STRIDE;
+  TwiddleRegs<M, V> tw;
+  tw.load(j, job.twM, 1);
+  const int total = job.H * job.nimg * job.nparts;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
+    const int q = u * C::LPB + g;
+    const bool ok = q < total;
+    const int qq = ok ? q : 0;
+    const int part = qq % job.nparts;
+    const int rest = qq / job.nparts;
+    const int img = rest % job.nimg;
+    const int c = rest / job.nimg;
+    float2 acc[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc[s] = make_float2(0.f, 0.f);
+    const float2* zimg = job.Z + img * job.z_img_stride - job.z_off_base;
+    const int q1 = ok ? job.col_ptr[c + 1] : 0;
+    int t = job.col_ptr[c] + part;
+    // software pipeline: the next spectrum's lines are in flight while the
+    // current one is transformed
+    float2 zn[V];
+    float pn[V];
+    if (t < q1) {
+      const int i = job.col_planes[t];
+      const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
+      const float* pb = job.psi + ((long long)i * job.H + c) * M;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        zn[s] = zb[j + G * s];
+        pn[s] = pb[j + G * s];
+      }
+    }
+    for (; t < q1; t += job.nparts) {
+      float2 v[V];
+      float ps[V];
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        v[s] = zn[s];
+        ps[s] = pn[s];
+      }
+      const int tn = t + job.nparts;
+      if (tn < q1) {
+        const int i = job.col_planes[tn];
+        const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
+        const float* pb = job.psi + ((long long)i * job.H + c) * M;
+#pragma unroll
+        for (int s = 0; s < V; ++s) {
+          zn[s] = zb[j + G * s];
+          pn[s] = pb[j + G * s];
+        }
+      }
+      fft_group<M, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        acc[s].x += ps[s] * v[s].x;
+        acc[s].y += ps[s] * v[s].y;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc[s] = cscale(acc[s], job.scale);
+    if constexpr (FUSED) {
+      fft_group<M, V, true, C::SYNC>(acc, j, my, tw);
+      if (ok) {
+        float2* ab = job.out + ((long long)img * job.H + c) * job.pitch;
+#pragma unroll
+        for (int s = 0; s < V; ++s) ab[j + G * s] = acc[s];
+      }
+    } else if (ok) {
+      float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * job.pitch;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        float2 val = acc[s];
+        if (job.accumulate) val = cadd(val, pb[j + G * s]);
+        pb[j + G * s] = val;
+      }
+    }
+  }
+}
+
+// For powers of two 64 <= M <= 1024 the body fits 128 registers (4 waves per
+// SIMD) with a few spills; other lengths (and the 12-value lanes of 3 * 2^k)
+// keep the compiler's own allocation.
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k_adj_lines(AdjLineJob job) {
+  adj_lines_body<M, FUSED>(job);
+}
+
+template <int M, bool FUSED>
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_wide(AdjLineJob job) {
+  adj_lines_body<M, FUSED>(job);
+}
+
+// Line kernels take the length M: powers of two and 3 * 2^k.
+#define FFST_COL_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
+  X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
+
+}  // namespace
+
+bool supported_length(int L) {
+  switch (L) {
+#define CASE(n) case n: return true;
+    FFST_COL_CASES(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse, const float2* parts, int nparts,
+                           long long part_stride, const float2* twM, hipStream_t s) {
+  if (nlines == 0) return hipSuccess;
+  switch (M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (nlines + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                     \
+    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
+    if (inverse)                                                                                  \
+      hipLaunchKernelGGL((k_line_fft<n, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
+                         part_stride, twM);                                                       \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_line_fft<n, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
+                         part_stride, twM);                                                       \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_COL_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
+  FwdLineJob job{a.F, a.psi, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.pitch, a.win, a.y_img_stride,
+                 a.y_off_base, a.Y, a.scale, a.twM};
+  if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.nlines * job.nimg;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    hipLaunchKernelGGL(k_fwd_lines<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),                \
+                       dim3(LineCfg<n>::THREADS), 0, s, job);                                     \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_COL_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
+  AdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psi, a.col_ptr, a.col_planes, a.N / 2 + 1,
+                 a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
+  if (job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.H * job.nimg * job.nparts;
+  switch (a.M) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
+    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
+    if constexpr (n >= 64 && n <= 1024 && n % 3 != 0) {                                            \
+      if (a.fused)                                                                                \
+        hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                       \
+      else                                                                                        \
+        hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                      \
+    } else {                                                                                      \
+      if (a.fused)                                                                                \
+        hipLaunchKernelGGL((k_adj_lines_wide<n, true>), grid, block, 0, s, job);                  \
+      else                                                                                        \
+        hipLaunchKernelGGL((k_adj_lines_wide<n, false>), grid, block, 0, s, job);                 \
+    }                                                                                             \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_COL_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ffst

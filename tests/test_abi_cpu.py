@@ -45,7 +45,9 @@ def test_spectra_rejects_bad_arguments(lib):
     assert lib.ffst_spectra(64, 64, 11, ctypes.byref(out)) == _lib.FFST_EINVAL
     assert lib.ffst_spectra(64, 64, 2, None) == _lib.FFST_EINVAL
     # valid transform sizes that this GPU path does not run
-    assert lib.ffst_spectra(384, 512, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(320, 512, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(512, 6144, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(512, 36, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(63, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(8192, 8192, 0, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     bad = _lib.ffst_options(2, 0)
@@ -93,5 +95,5 @@ def test_profiling_table(lib):
 
 def test_python_wrappers_raise(lib):
     with pytest.raises(_lib.FfstError) as e:
-        _lib.ffst_spectra(384, 512, 3)
+        _lib.ffst_spectra(320, 512, 3)
     assert e.value.status == _lib.FFST_EUNSUPPORTED
