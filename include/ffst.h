@@ -174,6 +174,66 @@ int ffst_adjoint_complex(const ffst_plan* plan, const float* coeffs, float* f, i
 int ffst_inverse_complex(const ffst_plan* plan, const float* coeffs, float* f, int batch,
                          void* ws, void* stream);
 
+/*
+ * Launch tuning of a plan (runtime knobs only; no setting changes what is
+ * computed beyond the order of the adjoint's floating-point sums):
+ *   nparts        number of partial sums the adjoint splits the sum over the
+ *                 spectra of a column into (1 .. 8; 0 = chosen from the batch)
+ *   blocks_per_cu persistent workgroups per compute unit of every kernel
+ *                 (1 .. 32; 0 = each kernel's default)
+ * The workspace size depends on nparts: query ffst_workspace_size after
+ * changing it.
+ */
+int ffst_set_tuning(ffst_plan* plan, int nparts, int blocks_per_cu);
+int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
+
+/*
+ * Autotuner: times forward + adjoint of `batch` images (f, read) for every
+ * setting nparts in {1, 2, 4, 8} x blocks_per_cu in {0, 1, 2, 4, 8, 16} whose
+ * workspace fits in ws_size bytes (the best of 3 runs after one warm-up, HIP
+ * events on `stream`), and keeps the fastest in the plan. coeffs (the
+ * coefficient buffer for the plan's kind, as for the transform calls) and
+ * out ([batch][M][N]) are scratch. Synchronous. *best_ms (may be NULL)
+ * receives the fastest time of one forward + adjoint.
+ */
+int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int batch, void* ws,
+              size_t ws_size, void* stream, double* best_ms);
+
+/*
+ * Uneven batches: images of different sizes in one call per direction.
+ *
+ * ffst_batch_create takes `count` images with sizes M[b] x N[b] and J[b]
+ * scales (J[b] <= 0: the default for that size) and the options shared by all
+ * of them (NULL = defaults). Images of the same (M, N, J) form a class and
+ * share one plan. The batch packs every class contiguously, classes in the
+ * order of their first image, images of a class in the given order:
+ * ffst_batch_layout writes, per image b (host arrays of count entries), the
+ * float offset of its image in the packed image buffer and of its
+ * coefficients ([eta_b][M_b][N_b], real or complex as the options say) in the
+ * packed coefficient buffer, and the two buffers' total float counts.
+ *
+ * A transform call runs every class on a stream of its own, forked from and
+ * joined back into `stream`, and is replayed as one HIP graph: the first call
+ * with a given (input, output, workspace) triple captures and instantiates
+ * the graph, later calls with the same triple launch it. The workspace must
+ * hold ffst_batch_workspace_size bytes (256-byte aligned); calls that run at
+ * the same time need separate workspaces. ffst_batch_tune runs ffst_tune for
+ * every class and drops the captured graphs.
+ */
+typedef struct ffst_batch ffst_batch;
+int ffst_batch_create(int count, const int* M, const int* N, const int* J, const ffst_options* opt,
+                      ffst_batch** out);
+int ffst_batch_info(const ffst_batch* batch, int* count, int* classes);
+int ffst_batch_class(const ffst_batch* batch, int cls, ffst_plan** plan, int* images);
+int ffst_batch_layout(const ffst_batch* batch, long long* img_offset, long long* coef_offset,
+                      long long* img_total, long long* coef_total);
+size_t ffst_batch_workspace_size(const ffst_batch* batch);
+int ffst_batch_forward(ffst_batch* batch, const float* f, float* coeffs, void* ws, void* stream);
+int ffst_batch_adjoint(ffst_batch* batch, const float* coeffs, float* f, void* ws, void* stream);
+int ffst_batch_inverse(ffst_batch* batch, const float* coeffs, float* f, void* ws, void* stream);
+int ffst_batch_tune(ffst_batch* batch, const float* f, float* coeffs, float* out, void* ws, void* stream);
+void ffst_batch_destroy(ffst_batch* batch);
+
 /* Release a plan (NULL is ignored). Synchronises the device first. */
 void ffst_destroy(ffst_plan* plan);
 

@@ -12,8 +12,13 @@ by hand-written HIP kernels for gfx950 behind the C ABI of include/ffst.h.
     c = plan.forward(x)                        # x: (B, 512, 512) float32 cuda
     y = plan.adjoint(c)                        # (B, 512, 512)
 
+    from paper_1202_1773_amd import BatchPlan  # images of several sizes
+    bp = BatchPlan([(256, 256), (384, 512), (1024, 1024)])
+    coeffs = bp.forward(bp.pack(images))       # one HIP graph launch
+
 PyTorch supplies device memory and the current stream only.
 """
 
 from ._lib import FfstError  # noqa: F401
+from .batch import BatchPlan  # noqa: F401
 from .plan import Plan  # noqa: F401

@@ -23,6 +23,10 @@ EXPORTED = [
     "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
     "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
     "ffst_inverse", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
+    "ffst_set_tuning", "ffst_get_tuning", "ffst_tune",
+    "ffst_batch_create", "ffst_batch_info", "ffst_batch_class", "ffst_batch_layout",
+    "ffst_batch_workspace_size", "ffst_batch_forward", "ffst_batch_adjoint", "ffst_batch_inverse",
+    "ffst_batch_tune", "ffst_batch_destroy",
     "ffst_destroy", "ffst_last_error", "ffst_profile_enable",
     "ffst_profile_read", "ffst_profile_reset", "ffst_num_kernels", "ffst_kernel_name",
 ]
@@ -66,6 +70,21 @@ def load():
         "ffst_forward_complex": (I, [P, P, P, I, P, P]),
         "ffst_adjoint_complex": (I, [P, P, P, I, P, P]),
         "ffst_inverse_complex": (I, [P, P, P, I, P, P]),
+        "ffst_set_tuning": (I, [P, I, I]),
+        "ffst_get_tuning": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_tune": (I, [P, P, P, P, I, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double)]),
+        "ffst_batch_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                  ctypes.POINTER(ffst_options), ctypes.POINTER(P)]),
+        "ffst_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_batch_class": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(I)]),
+        "ffst_batch_layout": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
+        "ffst_batch_workspace_size": (ctypes.c_size_t, [P]),
+        "ffst_batch_forward": (I, [P, P, P, P, P]),
+        "ffst_batch_adjoint": (I, [P, P, P, P, P]),
+        "ffst_batch_inverse": (I, [P, P, P, P, P]),
+        "ffst_batch_tune": (I, [P, P, P, P, P, P]),
+        "ffst_batch_destroy": (None, [P]),
         "ffst_destroy": (None, [P]),
         "ffst_last_error": (ctypes.c_char_p, []),
         "ffst_profile_enable": (I, [ctypes.c_uint]),
@@ -159,6 +178,88 @@ def ffst_adjoint_complex(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
 def ffst_inverse_complex(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
     _check(load().ffst_inverse_complex(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
                                        ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_inverse_complex")
+
+
+def ffst_set_tuning(plan, nparts, blocks_per_cu):
+    _check(load().ffst_set_tuning(plan, int(nparts), int(blocks_per_cu)), "ffst_set_tuning")
+
+
+def ffst_get_tuning(plan):
+    n = ctypes.c_int()
+    b = ctypes.c_int()
+    _check(load().ffst_get_tuning(plan, ctypes.byref(n), ctypes.byref(b)), "ffst_get_tuning")
+    return n.value, b.value
+
+
+def ffst_tune(plan, f_ptr, c_ptr, out_ptr, batch, ws_ptr, ws_size, stream_ptr):
+    best = ctypes.c_double()
+    _check(load().ffst_tune(plan, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), ctypes.c_void_p(out_ptr),
+                            int(batch), ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_size),
+                            ctypes.c_void_p(stream_ptr), ctypes.byref(best)), "ffst_tune")
+    return best.value
+
+
+def ffst_batch_create(Ms, Ns, Js, max_scale="max", shearlet=FFST_SHEARLET_MEYER, complex_shearlets=False, aux=3):
+    n = len(Ms)
+    arr = ctypes.c_int * n
+    opt = ffst_options(1 if max_scale == "min" else 0, int(shearlet), 1 if complex_shearlets else 0,
+                       aux_order(aux))
+    out = ctypes.c_void_p()
+    _check(load().ffst_batch_create(n, arr(*Ms), arr(*Ns), arr(*Js), ctypes.byref(opt), ctypes.byref(out)),
+           "ffst_batch_create")
+    return out.value
+
+
+def ffst_batch_info(batch):
+    c = ctypes.c_int()
+    k = ctypes.c_int()
+    _check(load().ffst_batch_info(batch, ctypes.byref(c), ctypes.byref(k)), "ffst_batch_info")
+    return c.value, k.value
+
+
+def ffst_batch_class(batch, cls):
+    p = ctypes.c_void_p()
+    n = ctypes.c_int()
+    _check(load().ffst_batch_class(batch, int(cls), ctypes.byref(p), ctypes.byref(n)), "ffst_batch_class")
+    return p.value, n.value
+
+
+def ffst_batch_layout(batch, count):
+    io = (ctypes.c_longlong * count)()
+    co = (ctypes.c_longlong * count)()
+    it = ctypes.c_longlong()
+    ct = ctypes.c_longlong()
+    _check(load().ffst_batch_layout(batch, io, co, ctypes.byref(it), ctypes.byref(ct)), "ffst_batch_layout")
+    return list(io), list(co), it.value, ct.value
+
+
+def ffst_batch_workspace_size(batch):
+    return int(load().ffst_batch_workspace_size(batch))
+
+
+def ffst_batch_forward(batch, f_ptr, c_ptr, ws_ptr, stream_ptr):
+    _check(load().ffst_batch_forward(batch, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), ctypes.c_void_p(ws_ptr),
+                                     ctypes.c_void_p(stream_ptr)), "ffst_batch_forward")
+
+
+def ffst_batch_adjoint(batch, c_ptr, f_ptr, ws_ptr, stream_ptr):
+    _check(load().ffst_batch_adjoint(batch, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), ctypes.c_void_p(ws_ptr),
+                                     ctypes.c_void_p(stream_ptr)), "ffst_batch_adjoint")
+
+
+def ffst_batch_inverse(batch, c_ptr, f_ptr, ws_ptr, stream_ptr):
+    _check(load().ffst_batch_inverse(batch, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), ctypes.c_void_p(ws_ptr),
+                                     ctypes.c_void_p(stream_ptr)), "ffst_batch_inverse")
+
+
+def ffst_batch_tune(batch, f_ptr, c_ptr, out_ptr, ws_ptr, stream_ptr):
+    _check(load().ffst_batch_tune(batch, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), ctypes.c_void_p(out_ptr),
+                                  ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_batch_tune")
+
+
+def ffst_batch_destroy(batch):
+    if batch:
+        load().ffst_batch_destroy(batch)
 
 
 def ffst_destroy(plan):

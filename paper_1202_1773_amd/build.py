@@ -16,7 +16,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffst.so")
-SOURCES = ["spectra.hip", "transform_rows.hip", "transform_cols.hip", "complex.hip", "api.hip"]
+SOURCES = ["spectra.hip", "transform_rows.hip", "transform_cols.hip", "complex.hip", "api.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

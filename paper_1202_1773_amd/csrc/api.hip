@@ -1,6 +1,7 @@
 // api.hip -- plan management and the C ABI declared in include/ffst.h.
 #include "../../include/ffst.h"
 #include "internal.hpp"
+#include "launch_cfg.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -44,16 +45,16 @@ struct ffst_plan {
   std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
   std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
   long long chunk_elems = 0;    // target size of one unit's compact buffer
+  int tune_nparts = 0;          // adjoint partial sums per line (0: heuristic)
+  int tune_blocks_per_cu = 0;   // persistent blocks per CU (0: per-kernel default)
   unsigned magic = 0;
 };
 
 namespace {
-
-constexpr unsigned kMagic = 0x46465354u;  // "FFST"
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int status, const char* fmt, ...) {
+int ffst::fail(int status, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -62,6 +63,10 @@ int fail(int status, const char* fmt, ...) {
   g_err = buf;
   return status;
 }
+
+namespace {
+
+constexpr unsigned kMagic = 0x46465354u;  // "FFST"
 
 int ok() { return FFST_OK; }
 
@@ -79,6 +84,7 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 unsigned g_mask = 0;
+bool g_profile_suspended = false;       // set while a graph is being captured
 std::vector<ProfRec> g_recs;
 std::vector<hipEvent_t> g_pool;  // events reused across timed launches
 double g_total_ms[KID_COUNT] = {};
@@ -97,7 +103,7 @@ hipEvent_t pooled_event() {
 
 template <class Fn>
 hipError_t timed(int id, hipStream_t s, Fn&& fn) {
-  if (!((g_mask >> id) & 1u)) return fn();
+  if (g_profile_suspended || !((g_mask >> id) & 1u)) return fn();
   ProfRec r{id, pooled_event(), pooled_event()};
   if (!r.a || !r.b) return fn();
   (void)hipEventRecord(r.a, s);
@@ -164,6 +170,10 @@ void release(void* ptr) {
   if (ptr) (void)hipFree(ptr);
 }
 
+void release_event(hipEvent_t e) {
+  if (e) (void)hipEventDestroy(e);
+}
+
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& src) {
   *dst = nullptr;
@@ -215,7 +225,7 @@ Schedule schedule(const ffst_plan* p, int batch) {
   const long long units = (long long)p->H * sc.chunk_imgs;
   const long long want = 8LL * 256;
   sc.nparts = (int)std::min<long long>(8, std::max<long long>(1, (want + units - 1) / units));
-  if (const char* e = std::getenv("FFST_NPARTS")) sc.nparts = std::max(1, std::min(8, std::atoi(e)));
+  if (p->tune_nparts > 0) sc.nparts = p->tune_nparts;
   sc.fused = (ngroups == 1 && sc.nparts == 1);
   sc.fa_bytes = align256((size_t)batch * p->pitch * p->H * sizeof(float2));
   sc.yz_bytes = align256((size_t)sc.chunk_imgs * (size_t)max_group * sizeof(float2));
@@ -335,10 +345,32 @@ int reject_kind(const ffst_plan* p, bool want_complex, const char* call) {
   return fail(FFST_EINVAL, "%s: the plan has %s shearlets", call, want_complex ? "real" : "complex");
 }
 
+// Applies a plan's persistent-grid setting to the launches of one call.
+struct TuningScope {
+  int saved;
+  explicit TuningScope(const ffst_plan* p) : saved(t_blocks_per_cu) { t_blocks_per_cu = p->tune_blocks_per_cu; }
+  ~TuningScope() { t_blocks_per_cu = saved; }
+};
+
 Windows plane_windows(const ffst_plan* p) { return Windows{p->d_lo, p->d_w, p->d_off}; }
 Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_w, p->d_img_off}; }
 
 }  // namespace
+
+void ffst::profile_suspend(bool on) { g_profile_suspended = on; }
+
+size_t ffst::workspace_upper_bound(const ffst_plan* p, int batch) {
+  if (!plan_ok(p) || batch <= 0) return 0;
+  ffst_plan* q = const_cast<ffst_plan*>(p);
+  const int saved = q->tune_nparts;
+  size_t most = 0;
+  for (int n = 1; n <= 8; ++n) {
+    q->tune_nparts = n;
+    most = std::max(most, ws_bytes(q, batch));
+  }
+  q->tune_nparts = saved;
+  return most;
+}
 
 extern "C" {
 
@@ -570,6 +602,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   int st = check_call(p, f, img * (size_t)std::max(batch, 0), coeffs, img * p->eta * (size_t)std::max(batch, 0),
                       batch, ws);
   if (st != FFST_OK || batch == 0) return st;
+  const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   float2* F = static_cast<float2*>(ws);
@@ -612,6 +645,7 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
   int st = check_call(p, coeffs, img * p->eta * (size_t)std::max(batch, 0), f, img * (size_t)std::max(batch, 0),
                       batch, ws);
   if (st != FFST_OK || batch == 0) return st;
+  const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   float2* A = static_cast<float2*>(ws);
@@ -661,6 +695,7 @@ int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int 
   const size_t nb = (size_t)std::max(batch, 0);
   int st = check_call(p, f, img * nb, coeffs, 2 * img * p->eta * nb, batch, ws);
   if (st != FFST_OK || batch == 0) return st;
+  const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   float2* F = static_cast<float2*>(ws);
@@ -702,6 +737,7 @@ int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int 
   const size_t nb = (size_t)std::max(batch, 0);
   int st = check_call(p, coeffs, 2 * img * p->eta * nb, f, img * nb, batch, ws);
   if (st != FFST_OK || batch == 0) return st;
+  const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   float2* A = static_cast<float2*>(ws);
@@ -744,6 +780,80 @@ int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int 
 
 int ffst_inverse_complex(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
   return ffst_adjoint_complex(p, coeffs, f, batch, ws, stream);
+}
+
+int ffst_set_tuning(ffst_plan* p, int nparts, int blocks_per_cu) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (nparts < 0 || nparts > 8) return fail(FFST_EINVAL, "nparts must be in [0, 8] (got %d)", nparts);
+  if (blocks_per_cu < 0 || blocks_per_cu > 32)
+    return fail(FFST_EINVAL, "blocks_per_cu must be in [0, 32] (got %d)", blocks_per_cu);
+  p->tune_nparts = nparts;
+  p->tune_blocks_per_cu = blocks_per_cu;
+  return ok();
+}
+
+int ffst_get_tuning(const ffst_plan* p, int* nparts, int* blocks_per_cu) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (nparts) *nparts = p->tune_nparts;
+  if (blocks_per_cu) *blocks_per_cu = p->tune_blocks_per_cu;
+  return ok();
+}
+
+int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch, void* ws, size_t ws_size,
+              void* stream, double* best_ms) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (batch < 1) return fail(FFST_EINVAL, "batch must be >= 1 (got %d)", batch);
+  if (!f || !coeffs || !out || !ws) return fail(FFST_EINVAL, "buffers must be non-NULL");
+  const bool cplx = p->opt.complex_shearlets == 1;
+  auto fwd = cplx ? ffst_forward_complex : ffst_forward;
+  auto adj = cplx ? ffst_adjoint_complex : ffst_adjoint;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    release_event(a);
+    return fail(FFST_EDEVICE, "ffst_tune: hipEventCreate failed");
+  }
+  const int parts[] = {1, 2, 4, 8};
+  const int per_cu[] = {0, 1, 2, 4, 8, 16};
+  const int saved_n = p->tune_nparts, saved_b = p->tune_blocks_per_cu;
+  double best = -1.0;
+  int best_n = saved_n, best_b = saved_b, st = FFST_OK;
+  for (int n : parts) {
+    for (int bc : per_cu) {
+      p->tune_nparts = n;
+      p->tune_blocks_per_cu = bc;
+      if (ws_bytes(p, batch) > ws_size) continue;
+      double t_min = -1.0;
+      for (int rep = 0; rep < 4 && st == FFST_OK; ++rep) {  // first run is a warm-up
+        (void)hipEventRecord(a, s);
+        st = fwd(p, f, coeffs, batch, ws, stream);
+        if (st == FFST_OK) st = adj(p, coeffs, out, batch, ws, stream);
+        (void)hipEventRecord(b, s);
+        float ms = 0.f;
+        if (st == FFST_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+          st = fail(FFST_EDEVICE, "ffst_tune: event timing failed");
+        if (st == FFST_OK && rep > 0 && (t_min < 0 || ms < t_min)) t_min = ms;
+      }
+      if (st != FFST_OK) break;
+      if (best < 0 || t_min < best) {
+        best = t_min;
+        best_n = n;
+        best_b = bc;
+      }
+    }
+    if (st != FFST_OK) break;
+  }
+  release_event(a);
+  release_event(b);
+  if (st != FFST_OK || best < 0) {
+    p->tune_nparts = saved_n;
+    p->tune_blocks_per_cu = saved_b;
+    return st != FFST_OK ? st : fail(FFST_EINVAL, "ffst_tune: workspace too small for every candidate");
+  }
+  p->tune_nparts = best_n;
+  p->tune_blocks_per_cu = best_b;
+  if (best_ms) *best_ms = best;
+  return ok();
 }
 
 void ffst_destroy(ffst_plan* p) {

@@ -1,0 +1,315 @@
+// batch.hip -- uneven batches: images of several sizes transformed by one
+// graph launch per direction (host code only; the kernels are the plans').
+//
+// Images of equal (M, N, J) form a class with one plan; every class runs the
+// plan's batched passes on a stream of its own, forked from a capture stream
+// by an event and joined back by one event per class. The whole fork/join is
+// captured into a HIP graph, instantiated once per (input, output, workspace)
+// triple and launched on the caller's stream; the classes' kernels can then
+// run side by side on the GPU with no host work between them.
+#include "../../include/ffst.h"
+#include "internal.hpp"
+#include "launch_cfg.hpp"
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
+using namespace ffst;
+
+namespace {
+
+constexpr unsigned kBatchMagic = 0x46464254u;  // "FFBT"
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct ffst_batch {
+  int count = 0;
+  bool cplx = false;
+  std::vector<ffst_plan*> plans;            // one per class
+  std::vector<int> cls_images;              // images per class
+  std::vector<long long> cls_img_off;       // float offsets of the class blocks
+  std::vector<long long> cls_coef_off;
+  std::vector<size_t> cls_ws_off, cls_ws_size;
+  std::vector<long long> img_off, coef_off; // per image, in the caller's order
+  long long img_total = 0, coef_total = 0;
+  size_t ws_total = 0;
+  int device = -1;
+  hipStream_t capture = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    const void* in = nullptr;
+    const void* out = nullptr;
+    const void* ws = nullptr;
+  } graphs[2];                              // 0: forward, 1: adjoint
+  unsigned magic = 0;
+};
+
+namespace {
+
+bool batch_ok(const ffst_batch* b) { return b && b->magic == kBatchMagic; }
+
+void drop_graphs(ffst_batch* b) {
+  for (auto& g : b->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = ffst_batch::Graph{};
+  }
+}
+
+void free_batch(ffst_batch* b) {
+  if (!b) return;
+  drop_graphs(b);
+  for (auto* p : b->plans) ffst_destroy(p);
+  for (auto s : b->streams)
+    if (s) (void)hipStreamDestroy(s);
+  for (auto e : b->joins)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  b->magic = 0;
+  delete b;
+}
+
+int plan_eta(const ffst_plan* p) {
+  int eta = 0;
+  ffst_plan_info(p, nullptr, nullptr, nullptr, &eta);
+  return eta;
+}
+
+void plan_size(const ffst_plan* p, int* M, int* N) { ffst_plan_info(p, M, N, nullptr, nullptr); }
+
+// Records the launches of one direction for every class, fork/join around
+// the capture stream, into a new executable graph.
+int capture(ffst_batch* b, int dir, const float* in, float* out, void* ws, hipGraphExec_t* exec) {
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return fail(FFST_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  profile_suspend(true);
+  int st = FFST_OK;
+  if ((e = hipEventRecord(b->fork, b->capture)) != hipSuccess)
+    st = fail(FFST_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+  const size_t nc = b->plans.size();
+  for (size_t c = 0; c < nc && st == FFST_OK; ++c) {
+    hipStream_t s = b->streams[c];
+    if ((e = hipStreamWaitEvent(s, b->fork, 0)) != hipSuccess) {
+      st = fail(FFST_EDEVICE, "hipStreamWaitEvent: %s", hipGetErrorString(e));
+      break;
+    }
+    void* cws = static_cast<char*>(ws) + b->cls_ws_off[c];
+    const ffst_plan* p = b->plans[c];
+    if (dir == 0) {
+      const float* f = in + b->cls_img_off[c];
+      float* co = out + b->cls_coef_off[c];
+      st = b->cplx ? ffst_forward_complex(p, f, co, b->cls_images[c], cws, s)
+                   : ffst_forward(p, f, co, b->cls_images[c], cws, s);
+    } else {
+      const float* co = in + b->cls_coef_off[c];
+      float* f = out + b->cls_img_off[c];
+      st = b->cplx ? ffst_adjoint_complex(p, co, f, b->cls_images[c], cws, s)
+                   : ffst_adjoint(p, co, f, b->cls_images[c], cws, s);
+    }
+    if (st == FFST_OK && (e = hipEventRecord(b->joins[c], s)) != hipSuccess)
+      st = fail(FFST_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    if (st == FFST_OK && (e = hipStreamWaitEvent(b->capture, b->joins[c], 0)) != hipSuccess)
+      st = fail(FFST_EDEVICE, "hipStreamWaitEvent: %s", hipGetErrorString(e));
+  }
+  profile_suspend(false);
+  // the capture is always ended, also after a failure, so the stream leaves capture mode
+  e = hipStreamEndCapture(b->capture, &graph);
+  if (st == FFST_OK && e != hipSuccess) st = fail(FFST_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  if (st == FFST_OK && (e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+    st = fail(FFST_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (graph) (void)hipGraphDestroy(graph);
+  return st;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+int run(ffst_batch* b, int dir, const float* in, float* out, void* ws, void* stream, const char* what) {
+  if (!batch_ok(b)) return fail(FFST_EBADPLAN, "%s: invalid batch", what);
+  if (!in || !out || !ws) return fail(FFST_EINVAL, "%s: buffers must be non-NULL", what);
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(FFST_EINVAL, "%s: workspace must be 256-byte aligned", what);
+  if (reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8)
+    return fail(FFST_EINVAL, "%s: input and output must be 8-byte aligned", what);
+  const size_t img_bytes = (size_t)b->img_total * sizeof(float), coef_bytes = (size_t)b->coef_total * sizeof(float);
+  const size_t in_bytes = dir == 0 ? img_bytes : coef_bytes, out_bytes = dir == 0 ? coef_bytes : img_bytes;
+  if (overlaps(in, in_bytes, out, out_bytes) || overlaps(ws, b->ws_total, in, in_bytes) ||
+      overlaps(ws, b->ws_total, out, out_bytes))
+    return fail(FFST_EINVAL, "%s: input, output and workspace must not overlap", what);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+    return fail(FFST_EINVAL, "%s: the current device is not the batch's device %d", what, b->device);
+  ffst_batch::Graph& g = b->graphs[dir];
+  if (!g.exec || g.in != in || g.out != out || g.ws != ws) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = ffst_batch::Graph{};
+    hipGraphExec_t exec = nullptr;
+    const int st = capture(b, dir, in, out, ws, &exec);
+    if (st != FFST_OK) return st;
+    g = ffst_batch::Graph{exec, in, out, ws};
+  }
+  const hipError_t e = hipGraphLaunch(g.exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(FFST_EDEVICE, "%s: hipGraphLaunch: %s", what, hipGetErrorString(e));
+  return FFST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffst_batch_create(int count, const int* M, const int* N, const int* J, const ffst_options* opt,
+                      ffst_batch** out) {
+  if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  if (count < 1) return fail(FFST_EINVAL, "count must be >= 1 (got %d)", count);
+  if (!M || !N || !J) return fail(FFST_EINVAL, "size arrays must be non-NULL");
+  ffst_batch* b = new (std::nothrow) ffst_batch();
+  if (!b) return fail(FFST_ENOMEM, "host allocation failed");
+  b->magic = kBatchMagic;
+  b->count = count;
+  b->cplx = opt && opt->complex_shearlets == 1;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    free_batch(b);
+    return fail(FFST_EDEVICE, "hipGetDevice failed");
+  }
+  (void)num_cus();  // device query done here, not while a graph is captured
+  // classes in the order of their first image
+  std::map<std::tuple<int, int, int>, int> index;
+  std::vector<int> cls_of(count);
+  for (int i = 0; i < count; ++i) {
+    ffst_plan* probe = nullptr;
+    const auto key = std::make_tuple(M[i], N[i], J[i]);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      const int st = ffst_spectra_ex(M[i], N[i], J[i], opt, &probe);
+      if (st != FFST_OK) {
+        free_batch(b);
+        return st;  // message set by ffst_spectra_ex
+      }
+      it = index.emplace(key, (int)b->plans.size()).first;
+      b->plans.push_back(probe);
+      b->cls_images.push_back(0);
+    }
+    cls_of[i] = it->second;
+    b->cls_images[it->second] += 1;
+  }
+  const size_t nc = b->plans.size();
+  const long long cmul = b->cplx ? 2 : 1;
+  b->cls_img_off.resize(nc);
+  b->cls_coef_off.resize(nc);
+  b->cls_ws_off.resize(nc);
+  b->cls_ws_size.resize(nc);
+  long long io = 0, co = 0;
+  size_t wo = 0;
+  for (size_t c = 0; c < nc; ++c) {
+    int m = 0, n = 0;
+    plan_size(b->plans[c], &m, &n);
+    const long long mn = (long long)m * n;
+    b->cls_img_off[c] = io;
+    b->cls_coef_off[c] = co;
+    io += mn * b->cls_images[c];
+    co += cmul * plan_eta(b->plans[c]) * mn * b->cls_images[c];
+    b->cls_ws_off[c] = wo;
+    b->cls_ws_size[c] = align256(workspace_upper_bound(b->plans[c], b->cls_images[c]));
+    wo += b->cls_ws_size[c];
+  }
+  b->img_total = io;
+  b->coef_total = co;
+  b->ws_total = std::max<size_t>(wo, 256);
+  b->img_off.resize(count);
+  b->coef_off.resize(count);
+  std::vector<int> seen(nc, 0);
+  for (int i = 0; i < count; ++i) {
+    const int c = cls_of[i];
+    int m = 0, n = 0;
+    plan_size(b->plans[c], &m, &n);
+    const long long mn = (long long)m * n;
+    b->img_off[i] = b->cls_img_off[c] + mn * seen[c];
+    b->coef_off[i] = b->cls_coef_off[c] + cmul * plan_eta(b->plans[c]) * mn * seen[c];
+    seen[c] += 1;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  b->streams.assign(nc, nullptr);
+  b->joins.assign(nc, nullptr);
+  for (size_t c = 0; c < nc && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&b->streams[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[c], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(FFST_EDEVICE, "stream/event creation: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return FFST_OK;
+}
+
+int ffst_batch_info(const ffst_batch* b, int* count, int* classes) {
+  if (!batch_ok(b)) return fail(FFST_EBADPLAN, "invalid batch");
+  if (count) *count = b->count;
+  if (classes) *classes = (int)b->plans.size();
+  return FFST_OK;
+}
+
+int ffst_batch_class(const ffst_batch* b, int cls, ffst_plan** plan, int* images) {
+  if (!batch_ok(b)) return fail(FFST_EBADPLAN, "invalid batch");
+  if (cls < 0 || cls >= (int)b->plans.size()) return fail(FFST_EINVAL, "class %d out of range", cls);
+  if (plan) *plan = b->plans[cls];
+  if (images) *images = b->cls_images[cls];
+  return FFST_OK;
+}
+
+int ffst_batch_layout(const ffst_batch* b, long long* img_offset, long long* coef_offset, long long* img_total,
+                      long long* coef_total) {
+  if (!batch_ok(b)) return fail(FFST_EBADPLAN, "invalid batch");
+  if (img_offset) std::copy(b->img_off.begin(), b->img_off.end(), img_offset);
+  if (coef_offset) std::copy(b->coef_off.begin(), b->coef_off.end(), coef_offset);
+  if (img_total) *img_total = b->img_total;
+  if (coef_total) *coef_total = b->coef_total;
+  return FFST_OK;
+}
+
+size_t ffst_batch_workspace_size(const ffst_batch* b) { return batch_ok(b) ? b->ws_total : 0; }
+
+int ffst_batch_forward(ffst_batch* b, const float* f, float* coeffs, void* ws, void* stream) {
+  return run(b, 0, f, coeffs, ws, stream, "ffst_batch_forward");
+}
+
+int ffst_batch_adjoint(ffst_batch* b, const float* coeffs, float* f, void* ws, void* stream) {
+  return run(b, 1, coeffs, f, ws, stream, "ffst_batch_adjoint");
+}
+
+int ffst_batch_inverse(ffst_batch* b, const float* coeffs, float* f, void* ws, void* stream) {
+  return run(b, 1, coeffs, f, ws, stream, "ffst_batch_inverse");
+}
+
+int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, void* ws, void* stream) {
+  if (!batch_ok(b)) return fail(FFST_EBADPLAN, "invalid batch");
+  if (!f || !coeffs || !out || !ws) return fail(FFST_EINVAL, "ffst_batch_tune: buffers must be non-NULL");
+  drop_graphs(b);
+  for (size_t c = 0; c < b->plans.size(); ++c) {
+    const int st = ffst_tune(b->plans[c], f + b->cls_img_off[c], coeffs + b->cls_coef_off[c], out + b->cls_img_off[c],
+                             b->cls_images[c], static_cast<char*>(ws) + b->cls_ws_off[c], b->cls_ws_size[c], stream,
+                             nullptr);
+    if (st != FFST_OK) return st;
+  }
+  return FFST_OK;
+}
+
+void ffst_batch_destroy(ffst_batch* b) {
+  if (!batch_ok(b)) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+}  // extern "C"

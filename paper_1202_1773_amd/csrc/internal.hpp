@@ -168,6 +168,18 @@ struct CAdjLineArgs {
 };
 hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s);
 
+// Error reporting shared by the C ABI files: stores the message returned by
+// ffst_last_error on this thread and returns `status`.
+int fail(int status, const char* fmt, ...);
+// While set, kernel timing is skipped (launches being captured into a graph).
+void profile_suspend(bool on);
+}  // namespace ffst
+
+struct ffst_plan;
+namespace ffst {
+// Workspace bytes a call with `batch` images needs under any tuning setting.
+size_t workspace_upper_bound(const ffst_plan* p, int batch);
+
 // Column lengths M and row lengths N the kernels are instantiated for:
 // powers of two in [8, 4096] and 3 * 2^k in [12, 3072].
 bool supported_length(int M);

@@ -85,9 +85,13 @@ inline int num_cus() {
   return n;
 }
 
+// Persistent blocks per CU for the launches of the current call on this
+// thread (0: the per-kernel default below); set from a plan's tuning.
+inline thread_local int t_blocks_per_cu = 0;
+
 // Persistent grids: enough blocks for the work, at most `per_cu` per CU.
 inline int grid_for(long long units, int threads) {
-  const int per_cu = threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8);
+  const int per_cu = t_blocks_per_cu > 0 ? t_blocks_per_cu : (threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8));
   const long long cap = (long long)num_cus() * per_cu;
   return (int)(units < cap ? (units > 0 ? units : 1) : cap);
 }

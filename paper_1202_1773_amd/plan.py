@@ -93,6 +93,33 @@ class Plan:
     def inverse(self, c, out=None, ws=None):
         return self.adjoint(c, out=out, ws=ws)
 
+    # ---------------------------------------------------------------- tuning
+    def tuning(self):
+        """(nparts, blocks_per_cu) of the plan; 0 means the built-in choice."""
+        return _lib.ffst_get_tuning(self._h)
+
+    def set_tuning(self, nparts=0, blocks_per_cu=0):
+        _lib.ffst_set_tuning(self._h, nparts, blocks_per_cu)
+        self._ws.clear()
+
+    def tune(self, x):
+        """Autotune the launch settings for forward + adjoint of the images x
+        ((M, N) or (B, M, N), float32); returns the best time in ms."""
+        self._check(x, (self.M, self.N))
+        xb = x.reshape(-1, self.M, self.N)
+        B = xb.shape[0]
+        saved = self.tuning()
+        _lib.ffst_set_tuning(self._h, 8, saved[1])        # largest workspace of any setting
+        ws_size = self.workspace_size(B)
+        _lib.ffst_set_tuning(self._h, *saved)
+        ws = torch.empty(ws_size + 256, dtype=torch.uint8, device=self.device)
+        ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+        c = torch.empty((B, self.eta, self.M, self.N), dtype=self.coef_dtype, device=self.device)
+        y = torch.empty_like(xb)
+        best = _lib.ffst_tune(self._h, xb.data_ptr(), c.data_ptr(), y.data_ptr(), B, ptr, ws_size, self._stream())
+        self._ws.clear()
+        return best
+
     # --------------------------------------------------------------- helpers
     def spectra(self, full_plane=False):
         """The plan's float32 spectra, (eta, M, N/2+1) or (eta, M, N); the

@@ -74,3 +74,22 @@ def config2_batch(B=16, first_seed=201):
 def config5_image():
     """2048 x 2048, 200 ellipses, noise N(0, 0.1^2), seed 501."""
     return cartoon(2048, 2048, n_ellipses=200, n_halfplanes=0, sigma=0.1, seed=501)
+
+
+UNEVEN_SIZES = [(256, 256), (384, 512), (512, 512), (768, 1024), (1024, 1024)]
+
+
+def uneven_sizes(count=64, seed=401):
+    """Image sizes of the uneven batch: drawn uniformly from UNEVEN_SIZES with
+    numpy.random.default_rng(seed); J = 3 where the larger side is <= 512,
+    else 4. Returns (sizes, Js)."""
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, len(UNEVEN_SIZES), size=count)
+    sizes = [UNEVEN_SIZES[i] for i in idx]
+    return sizes, [3 if max(m, n) <= 512 else 4 for m, n in sizes]
+
+
+def uneven_images(sizes, first_seed=402):
+    """One cartoon per size (10 half-planes, 20 ellipses, noise N(0, 0.1^2)),
+    seeds first_seed, first_seed + 1, ..."""
+    return [cartoon(m, n, 20, 10, 0.1, first_seed + b) for b, (m, n) in enumerate(sizes)]

@@ -76,6 +76,20 @@ def test_calls_reject_bad_plans(lib):
     assert lib.ffst_forward_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_adjoint_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_inverse_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_set_tuning(None, 0, 0) == _lib.FFST_EBADPLAN
+    assert lib.ffst_get_tuning(None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_tune(None, None, None, None, 1, None, 0, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_forward(None, None, None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_adjoint(None, None, None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_inverse(None, None, None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_tune(None, None, None, None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_info(None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_class(None, 0, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_layout(None, None, None, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_batch_workspace_size(None) == 0
+    lib.ffst_batch_destroy(None)
+    out = ctypes.c_void_p()
+    assert lib.ffst_batch_create(0, None, None, None, None, ctypes.byref(out)) == _lib.FFST_EINVAL
     assert lib.ffst_get_spectra(None, None, 0) == _lib.FFST_EBADPLAN
     assert lib.ffst_plan_windows(None, None, None) == _lib.FFST_EBADPLAN
     assert "plan" in _lib.ffst_last_error()
