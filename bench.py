@@ -14,6 +14,12 @@ Prints ONE JSON line:
                the current kernel sources, else null
   path_roofline  the whole step's algorithmic bytes over the step time
   cpu_baseline the FP64 CPU oracle on a bounded sample (1 thread)
+  complex_shearlets  the same images with complex (one-sided) shearlets
+  uneven_batch the 64-image uneven batch (256^2 .. 1024^2, seed 401) through
+               one HIP graph launch per direction, with the built-in launch
+               settings and after the autotuner
+The batched and plain plans are autotuned (launch settings only) before any
+timing unless --no-tune is given.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
 """
@@ -90,6 +96,92 @@ def cpu_baseline(M, N, J, images):
                       f"{dt:.1f} s on {cpu_model()} (os.cpu_count()={os.cpu_count()})"}
 
 
+def nnz_half(plan):
+    """Nonzero half-plane spectrum values of a plan (read once per direction)."""
+    return int((plan.spectra(full_plane=False) != 0).sum().item())
+
+
+def time_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_uneven(steps, warmup, tune):
+    """The uneven batch: 64 images drawn from 256^2 .. 1024^2 (seed 401), one
+    graph launch per direction; forward + adjoint per step."""
+    import torch
+    from paper_1202_1773_amd import BatchPlan, Plan
+    from paper_1202_1773_amd.synthetic import uneven_images, uneven_sizes
+
+    sizes, Js = uneven_sizes()
+    imgs = uneven_images(sizes)
+    bp = BatchPlan(sizes, Js)
+    f = bp.pack([torch.from_numpy(i) for i in imgs])
+    c = bp.empty_coefficients()
+    y = bp.empty_images()
+
+    def step():
+        bp.forward(f, out=c)
+        bp.adjoint(c, out=y)
+
+    coef = sum(e * m * n for e, (m, n) in zip(bp.etas, sizes))
+    pix = sum(m * n for m, n in sizes)
+    nnz = 0
+    for key in dict.fromkeys(zip(sizes, Js)):
+        (m, n), j = key
+        p = Plan(m, n, j)
+        nnz += nnz_half(p)
+        p.close()
+    b_alg = 4 * (2 * coef + 2 * pix + 2 * nnz)
+    t_default = time_steps(step, steps, warmup)
+    rec = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+              for a, b in zip(bp.images(y), [torch.from_numpy(i).to(y.device) for i in imgs]))
+    out = {"images": len(sizes), "classes": bp.classes, "coefficients": coef,
+           "ms_per_step": round(t_default * 1e3, 4), "value": round(coef / t_default / 1e9, 3), "unit": "Gcoef/s",
+           "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t_default / 1e9 / HBM_PEAK_GBS, 4),
+           "reconstruction_rel_l2_max": rec}
+    if tune:
+        bp.tune(f)
+        t_tuned = time_steps(step, steps, warmup)
+        out["tuned"] = {"ms_per_step": round(t_tuned * 1e3, 4), "value": round(coef / t_tuned / 1e9, 3),
+                        "path_frac": round(b_alg / t_tuned / 1e9 / HBM_PEAK_GBS, 4),
+                        "class_tuning": bp.class_tuning()}
+    bp.close()
+    return out
+
+
+def bench_complex(x, M, N, J, steps, warmup):
+    """Complex shearlets on the headline images: forward + adjoint per step."""
+    import torch
+    from paper_1202_1773_amd import Plan
+
+    plan = Plan(M, N, J, complex_shearlets=True)
+    B = x.shape[0]
+    c = torch.empty((B, plan.eta, M, N), dtype=torch.complex64, device=x.device)
+    y = torch.empty_like(x)
+
+    def step():
+        plan.forward(x, out=c)
+        plan.adjoint(c, out=y)
+
+    t = time_steps(step, steps, warmup)
+    coef = B * plan.eta * M * N
+    # complex coefficients: 8 bytes each, written then read
+    b_alg = 2 * 8 * coef + 2 * 4 * B * M * N + 2 * 4 * int((plan.spectra(full_plane=True) != 0).sum().item())
+    rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+    plan.close()
+    return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
+            "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
+            "reconstruction_rel_l2": rec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +192,9 @@ def main():
     ap.add_argument("--scales", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the uneven-batch and complex-shearlet measurements")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in launch settings only")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -112,7 +207,7 @@ def main():
     import numpy as np
     import torch
     from paper_1202_1773_amd import Plan, _lib
-    from paper_1202_1773_amd.synthetic import config2_batch
+    from paper_1202_1773_amd.synthetic import cartoon_batch, config2_batch
 
     M = N = args.size
     J = args.scales
@@ -120,18 +215,23 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
-    plan = Plan(M, N, J)
+    plan = Plan(M, N, J)            # batched form: B images per call
+    plan1 = Plan(M, N, J)           # plain form: one image per call
     eta = plan.eta
-    imgs = config2_batch(B) if M == 512 else np.stack(
-        [__import__("paper_1202_1773_amd.synthetic", fromlist=["cartoon"]).cartoon(M, N, 20, 10, 0.1, 201 + b)
-         for b in range(B)])
+    imgs = config2_batch(B) if M == 512 else cartoon_batch(M, N, range(201, 201 + B))
     x = torch.from_numpy(imgs).to(dev)
     c = torch.empty((B, eta, M, N), dtype=torch.float32, device=dev)
     y = torch.empty((B, M, N), dtype=torch.float32, device=dev)
     c1 = torch.empty((eta, M, N), dtype=torch.float32, device=dev)
     y1 = torch.empty((M, N), dtype=torch.float32, device=dev)
+    tuning = None
+    if not args.no_tune:
+        # launch settings picked by the autotuner, per plan, before any timing
+        plan.tune(x)
+        plan1.tune(x[0])
+        tuning = {"batched": plan.tuning(), "plain": plan1.tuning()}
     plan.workspace(B)
-    plan.workspace(1)
+    plan1.workspace(1)
 
     def step_batched():
         plan.forward(x, out=c)
@@ -139,8 +239,8 @@ def main():
 
     def step_plain():
         for b in range(B):
-            plan.forward(x[b], out=c1)
-            plan.adjoint(c1, out=y1)
+            plan1.forward(x[b], out=c1)
+            plan1.adjoint(c1, out=y1)
 
     # warm-up, then one short pass per kernel (only that kernel bracketed by
     # HIP events, so host-side work never lands inside a bracket) to find
@@ -227,7 +327,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"FFST forward+adjoint, {B} cartoon images {M}x{N} per call, J={J} "
                                f"({eta} spectra), batched form; plain form = 1 image per call",
-                   "M": M, "N": N, "J": J, "eta": eta, "batch": B, "parallelism": "single GPU"},
+                   "M": M, "N": N, "J": J, "eta": eta, "batch": B, "parallelism": "single GPU",
+                   "launch_tuning": tuning},
         "plain": {"value": round(value_plain, 3), "unit": "Gcoef/s",
                   "ms_per_step": round(t_plain / plain_steps * 1e3, 4),
                   "batched_over_plain": round(value / value_plain, 3)},
@@ -257,7 +358,13 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 4 * n
 
+    if not args.no_extras:
+        extra_steps = max(3, args.steps // 5)
+        out["complex_shearlets"] = bench_complex(x, M, N, J, extra_steps, 2)
+        out["uneven_batch"] = bench_uneven(extra_steps, 2, not args.no_tune)
+
     plan.close()
+    plan1.close()
     del c, y, x
     torch.cuda.empty_cache()
 

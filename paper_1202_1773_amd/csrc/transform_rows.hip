@@ -68,8 +68,10 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
   const int j = threadIdx.x % G;
   const int rb = SMALL ? job.rb : C::RB;
   const int tr = threadIdx.x % rb;        // row (transpose phase)
-  // first column (transpose phase); threads beyond rb * (NT / rb) sit out
-  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
+  // first column (transpose phase); with a runtime rb that does not divide
+  // NT, threads beyond rb * (NT / rb) sit out (with rb = RB every thread
+  // takes part, and the bound stays a compile-time fact)
+  const int tc = (!SMALL || threadIdx.x < rb * (NT / rb)) ? threadIdx.x / rb : (1 << 29);
   const int cstep = NT / rb;
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
   const int j = threadIdx.x % G;
   const int rb = SMALL ? job.rb : C::RB;
   const int tr = threadIdx.x % rb;
-  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
+  const int tc = (!SMALL || threadIdx.x < rb * (NT / rb)) ? threadIdx.x / rb : (1 << 29);
   float2* my = lds + g * C::STRIDE;
   TwiddleRegs<L, V> tw;
   tw.load(j, job.twN, 2);
