@@ -25,7 +25,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
 """
 
 import argparse
-import hashlib
 import json
 import os
 import platform
@@ -35,18 +34,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1202_1773_amd.build import source_sha  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gcoef/s fwd+adjoint @512² J=3 FP32 (%HBM roofline); batched vs plain"
-KERNEL_SOURCES = ["fft_core.hpp", "launch_cfg.hpp", "internal.hpp", "spectra.hip", "transform_rows.hip",
-                  "transform_cols.hip", "complex.hip", "api.hip"]
-
-
-def source_hash():
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1202_1773_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def committed_traffic(kernel, M, N, J, B):
@@ -55,7 +46,7 @@ def committed_traffic(kernel, M, N, J, B):
     path = os.path.join(ROOT, "profiles", "traffic_ffst_512x512_J3_B16.md")
     if not os.path.exists(path):
         return None
-    want = source_hash()
+    want = source_sha()
     for line in open(path):
         if line.startswith("TRAFFIC "):
             rec = json.loads(line[len("TRAFFIC "):])
@@ -346,7 +337,7 @@ def main():
                           "nnz_half_spectra": nnz_half},
         "kernels_ms_per_step": {k: round(v[0], 5) for k, v in per_kernel.items()},
         "check": {"reconstruction_rel_l2": rec_err},
-        "source_sha": source_hash(),
+        "source_sha": source_sha(),
     }
 
     if args.copy_calibration_mb:

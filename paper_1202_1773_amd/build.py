@@ -7,6 +7,7 @@ link. Packed FP32 instructions are disabled for all device code
 (-Xclang -target-feature -Xclang -packed-fp32-ops).
 """
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -24,6 +25,19 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 NOISE = "packed-fp32-ops"
+
+
+def source_sha():
+    """Short hash of every kernel and C ABI source (csrc/*.hip, csrc/*.hpp and
+    include/ffst.h), to tie measurements to the code they were taken on."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    for name in files:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    with open(os.path.join(os.path.dirname(HERE), "include", "ffst.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _run(cmd):

@@ -1,14 +1,36 @@
-"""Summarise a rocprofv3 kernel trace (rocpd SQLite database) per kernel and
-launch shape: launches, average and total duration. Used to produce the
-text summaries kept under profiles/.
+"""Summaries of rocprofv3 output, as kept under profiles/.
+
+Kernel trace (rocpd SQLite database), per kernel and launch shape:
 
     python -m paper_1202_1773_amd.profile_summary <run_results.db>
+
+HBM traffic from two counter-collection runs (one with FETCH_SIZE, one with
+WRITE_SIZE; CSV output). Both counters are scaled by what they read for the
+largest plain device copy in the same runs (the benchmark's calibration copy
+of a known size), then averaged per launch of each labelled kernel shape:
+
+    python -m paper_1202_1773_amd.profile_summary --pmc <fetch_dir> <write_dir> \\
+        --copy-mib 256 --workload 512 512 3 16 \\
+        --label "k_r2c_rows(planes)=k_r2c_rows<256, false>@2048" ...
+
+Each label maps a kernel name of the library's timing table to a compiled
+kernel and a grid size in workgroups; one "TRAFFIC {json}" line is printed
+per label, tied to the kernel sources by their hash.
 """
 
+import argparse
 import collections
+import csv
+import glob
+import json
+import os
 import re
 import sqlite3
-import sys
+
+
+def short_name(name):
+    m = re.search(r"(k_[a-z0-9_]+(<[^>]*>)?)", name)
+    return m.group(1) if m else name[:48]
 
 
 def summarize(db):
@@ -17,9 +39,7 @@ def summarize(db):
                        "from kernels").fetchall()
     agg = collections.defaultdict(list)
     for name, gx, gy, wx, dur, lds, scr in rows:
-        m = re.search(r"(k_[a-z0-9_]+(<[^>]*>)?)", name)
-        short = m.group(1) if m else name[:48]
-        agg[(short, gx // max(wx, 1), gy, wx, lds, scr)].append(dur)
+        agg[(short_name(name), gx // max(wx, 1), gy, wx, lds, scr)].append(dur)
     total = sum(sum(v) for k, v in agg.items() if k[0].startswith("k_"))
     out = ["| kernel | blocks | wg | LDS B | scratch | launches | avg us | share |",
            "|---|---|---|---|---|---|---|---|"]
@@ -31,5 +51,80 @@ def summarize(db):
     return "\n".join(out)
 
 
+def read_counters(run_dir, counter):
+    """(kernel name, blocks) -> list of counter values (KiB per dispatch)."""
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {run_dir}")
+    out = collections.defaultdict(list)
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            wg = max(int(float(r.get("Workgroup_Size", 1) or 1)), 1)
+            blocks = int(float(r.get("Grid_Size", 0) or 0)) // wg
+            out[(r["Kernel_Name"], blocks)].append(float(r["Counter_Value"]))
+    return out
+
+
+def calibration(fetch, write, copy_mib):
+    """Scale factors from the plain copy: the non-library dispatch that
+    fetched the most, whose bytes read and written are both copy_mib MiB."""
+    cands = [(max(v), k) for k, v in fetch.items() if not short_name(k[0]).startswith("k_")]
+    if not cands:
+        raise RuntimeError("no copy dispatch in the fetch run")
+    kib = max(cands)[0]
+    key = max(cands)[1]
+    wkib = max(write.get(key, [0.0]))
+    if wkib <= 0:
+        raise RuntimeError("copy dispatch missing from the write run")
+    want = copy_mib * 1024.0
+    return want / kib, want / wkib, key[0]
+
+
+def traffic(fetch_dir, write_dir, copy_mib, workload, labels, sha):
+    fetch = read_counters(fetch_dir, "FETCH_SIZE")
+    write = read_counters(write_dir, "WRITE_SIZE")
+    ff, wf, copy_name = calibration(fetch, write, copy_mib)
+    lines = [f"Calibration: copy of {copy_mib} MiB (`{short_name(copy_name)}`): FETCH_SIZE x{ff:.3f}, "
+             f"WRITE_SIZE x{wf:.3f}", "",
+             "| kernel | compiled kernel | blocks | launches | FETCH KiB | WRITE KiB | HBM bytes / launch |",
+             "|---|---|---|---|---|---|---|"]
+    recs = []
+    for label in labels:
+        api, rest = label.split("=", 1)
+        kname, blocks = rest.rsplit("@", 1)
+        blocks = int(blocks)
+        fv = [v for (n, b), vals in fetch.items() if short_name(n) == kname and b == blocks for v in vals]
+        wv = [v for (n, b), vals in write.items() if short_name(n) == kname and b == blocks for v in vals]
+        if not fv or not wv:
+            raise RuntimeError(f"no dispatch of {kname} with {blocks} blocks")
+        f_kib = sum(fv) / len(fv)
+        w_kib = sum(wv) / len(wv)
+        nbytes = int(round((f_kib * ff + w_kib * wf) * 1024))
+        lines.append(f"| {api} | {kname} | {blocks} | {len(fv)} | {f_kib:.0f} | {w_kib:.0f} | {nbytes} |")
+        recs.append({"kernel": api, "compiled": kname, "blocks": blocks, "source_sha": sha,
+                     "workload": workload, "bytes_per_launch": nbytes,
+                     "fetch_bytes": int(round(f_kib * ff * 1024)), "write_bytes": int(round(w_kib * wf * 1024))})
+    lines.append("")
+    lines += ["TRAFFIC " + json.dumps(r) for r in recs]
+    return "\n".join(lines)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("db", nargs="?")
+    ap.add_argument("--pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--workload", type=int, nargs=4, metavar=("M", "N", "J", "B"))
+    ap.add_argument("--label", action="append", default=[])
+    args = ap.parse_args()
+    if args.pmc:
+        from .build import source_sha
+        print(traffic(args.pmc[0], args.pmc[1], args.copy_mib, args.workload, args.label, source_sha()))
+    else:
+        print(summarize(args.db))
+
+
 if __name__ == "__main__":
-    print(summarize(sys.argv[1]))
+    main()
