@@ -48,8 +48,11 @@ def committed_traffic(kernel, M, N, J, B):
         return None
     want = source_sha()
     for line in open(path):
-        if line.startswith("TRAFFIC "):
-            rec = json.loads(line[len("TRAFFIC "):])
+        if line.startswith("TRAFFIC {"):
+            try:
+                rec = json.loads(line[len("TRAFFIC "):])
+            except ValueError:
+                continue
             if (rec.get("kernel") == kernel and rec.get("source_sha") == want
                     and rec.get("workload") == [M, N, J, B]):
                 return rec["bytes_per_launch"]
