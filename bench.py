@@ -18,6 +18,7 @@ Prints ONE JSON line:
   uneven_batch the 64-image uneven batch (256^2 .. 1024^2, seed 401) through
                one HIP graph launch per direction, with the built-in launch
                settings and after the autotuner
+  large_image  one 2048 x 2048 image, J = 5 (125 spectra)
 The batched and plain plans are autotuned (launch settings only) before any
 timing unless --no-tune is given.
 
@@ -174,6 +175,35 @@ def bench_complex(x, M, N, J, steps, warmup):
     return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
             "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
             "reconstruction_rel_l2": rec}
+
+
+def bench_large(steps, warmup, tune):
+    """One 2048 x 2048 image, J = 5 (125 spectra), forward + adjoint per step."""
+    import torch
+    from paper_1202_1773_amd import Plan
+    from paper_1202_1773_amd.synthetic import config5_image
+
+    M = N = 2048
+    plan = Plan(M, N, 5)
+    x = torch.from_numpy(config5_image()).to("cuda")
+    c = torch.empty((plan.eta, M, N), dtype=torch.float32, device=x.device)
+    y = torch.empty_like(x)
+    if tune:
+        plan.tune(x)
+
+    def step():
+        plan.forward(x, out=c)
+        plan.adjoint(c, out=y)
+
+    t = time_steps(step, steps, warmup)
+    coef = plan.eta * M * N
+    b_alg = 4 * (2 * coef + 2 * M * N + 2 * nnz_half(plan))
+    rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+    out = {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
+           "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
+           "reconstruction_rel_l2": rec, "launch_tuning": plan.tuning()}
+    plan.close()
+    return out
 
 
 def main():
@@ -356,6 +386,7 @@ def main():
         extra_steps = max(3, args.steps // 5)
         out["complex_shearlets"] = bench_complex(x, M, N, J, extra_steps, 2)
         out["uneven_batch"] = bench_uneven(extra_steps, 2, not args.no_tune)
+        out["large_image"] = bench_large(extra_steps, 2, not args.no_tune)
 
     plan.close()
     plan1.close()
