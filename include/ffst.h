@@ -194,7 +194,8 @@ int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
  * events on `stream`), and keeps the fastest in the plan. coeffs (the
  * coefficient buffer for the plan's kind, as for the transform calls) and
  * out ([batch][M][N]) are scratch. Synchronous. *best_ms (may be NULL)
- * receives the fastest time of one forward + adjoint.
+ * receives the fastest time of one forward + adjoint. The tuning calls change
+ * the plan: no other call may use the plan while they run.
  */
 int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int batch, void* ws,
               size_t ws_size, void* stream, double* best_ms);
@@ -218,7 +219,10 @@ int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int ba
  * the graph, later calls with the same triple launch it. The workspace must
  * hold ffst_batch_workspace_size bytes (256-byte aligned); calls that run at
  * the same time need separate workspaces. ffst_batch_tune runs ffst_tune for
- * every class and drops the captured graphs.
+ * every class and drops the captured graphs; a graph captured before a class
+ * plan's settings were changed otherwise keeps the settings it was captured
+ * with (its results are the same). ffst_batch_class returns a class's plan
+ * (owned by the batch) and its image count.
  */
 typedef struct ffst_batch ffst_batch;
 int ffst_batch_create(int count, const int* M, const int* N, const int* J, const ffst_options* opt,
