@@ -35,6 +35,7 @@ struct CRowJob {
                             //   (win.off[plane] - z_off_base) + m*zp + r
   long long x_img_stride, z_img_stride, z_off_base;
   int nimg, nplanes, plane0, M, rb, zp;
+  int stream;               // k_c2c_rows_fwd: read x with non-temporal loads
   float inv_nplanes;
   Windows win;
   const float2* twN;        // exp(-2 pi i m / L), m < L
@@ -126,8 +127,13 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
     const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
     const float2* xr = job.x + ru.img * job.x_img_stride +
                        ((long long)ru.plane * job.M + ru.r0 + (row_ok ? g : 0)) * L;
+    if (job.stream) {
 #pragma unroll
-    for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+      for (int s = 0; s < V; ++s) dst[s] = row_ok ? load_stream(xr + j + G * s) : make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+    }
   };
 
   float2 nxt[V];
@@ -179,6 +185,7 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob
   const int total = job.nlines * job.nimg;
   float2 fn[V];
   float pn[V];
+  // units image by image, lines ordered by the F column they read
   auto load_unit = [&](int u) {
     const int q = u * C::LPB + g;
     const int qq = q < total ? q : 0;
@@ -346,7 +353,8 @@ CRowJob make_crow_job(const CRowArgs& a, int rb_max) {
   j.nplanes = a.nplanes;
   j.plane0 = a.plane0;
   j.M = a.M;
-  j.rb = rows_per_block(a.M, rb_max);
+  j.rb = rows_per_launch(a.M, rb_max, (long long)a.nimg * a.nplanes);
+  j.stream = (long long)a.nimg * a.nplanes * a.M * a.N * (long long)sizeof(float2) > kStreamBytes;
   j.zp = a.zp;
   j.inv_nplanes = 1.0f / (float)a.nplanes;
   j.win = a.win;

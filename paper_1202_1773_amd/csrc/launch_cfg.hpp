@@ -38,25 +38,32 @@ __device__ __forceinline__ int mirror_index(int r, int L) { return r == 0 ? 0 : 
 // one row, both touch distinct banks.
 __host__ __device__ constexpr int lds_stride(int L, int V) { return stride_mod32(lds_group_len(L, V), 17); }
 
+// Rows per block of the row kernels: 16 (128-byte column segments in the
+// transposed phase) while that keeps a block at <= 512 threads, whose 256
+// registers per lane hold a pipelined row FFT without spilling; longer rows
+// take fewer rows per block (512 / G).
+__host__ __device__ constexpr int row_block_rows(int G) {
+  return G <= 16 ? 256 / G : (G <= 32 ? 16 : 512 / G);
+}
+
 // Real rows of length N = 2L (complex FFT of length L), RB rows per block.
 template <int L>
 struct RowCfg {
   static constexpr int V = line_values(L);
   static constexpr int G = L / V;                      // lanes per row
   static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 8;
+  static constexpr int RB = row_block_rows(G);
   static constexpr int THREADS = RB * G;
   static constexpr int STRIDE = lds_stride(L, V);
 };
 
-// Complex rows of length L (complex FFT of length L), RB rows per block; at
-// most 1024 threads and about 140 KB of LDS per block.
+// Complex rows of length L (complex FFT of length L), RB rows per block.
 template <int L>
 struct CRowCfg {
   static constexpr int V = line_values(L);
   static constexpr int G = L / V;
   static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int RB = G <= 64 ? (256 / G > 16 ? 256 / G : 16) : 1024 / G;
+  static constexpr int RB = row_block_rows(G);
   static constexpr int THREADS = RB * G;
   static constexpr int STRIDE = lds_stride(L, V);
 };
@@ -94,6 +101,27 @@ inline int grid_for(long long units, int threads) {
   const int per_cu = t_blocks_per_cu > 0 ? t_blocks_per_cu : (threads >= 1024 ? 2 : (threads >= 512 ? 4 : 8));
   const long long cap = (long long)num_cus() * per_cu;
   return (int)(units < cap ? (units > 0 ? units : 1) : cap);
+}
+
+// Loads of data that is read once and not soon again (the coefficients of a
+// large batch): non-temporal, so they stream past the caches instead of
+// evicting the intermediates the next kernel reads back.
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const unsigned long long b = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+  float2 v;
+  __builtin_memcpy(&v, &b, sizeof v);
+  return v;
+}
+
+// Reads above this size (about half the 256 MB Infinity Cache) use load_stream.
+constexpr long long kStreamBytes = 128LL << 20;
+
+// Rows per block for a launch of `rows_total` rows: the fixed block height,
+// halved (down to 4 rows) while the launch would have fewer blocks than CUs.
+inline int rows_per_launch(int M, int rb_max, long long units_of_planes) {
+  int rb = rows_per_block(M, rb_max);
+  while (rb > 4 && units_of_planes * (M / rb) < num_cus()) rb /= 2;
+  return rb;
 }
 
 // A unit of the row kernels: rows r0 .. r0 + rb - 1 of plane `plane` of

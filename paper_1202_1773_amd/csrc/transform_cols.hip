@@ -82,8 +82,11 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob jo
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.nlines * job.nimg;
-  // software pipeline: the next unit's F and Psi lines are loaded while the
-  // current line is transformed
+  // Units run image by image, lines ordered by column, so neighbouring units
+  // share F[c] (measured faster than running the images of one line side by
+  // side, which would share the Psi line instead). Software pipeline: the
+  // next unit's F and Psi lines are loaded while the current line is
+  // transformed.
   float2 fn[V];
   float pn[V];
   auto load_unit = [&](int u) {
@@ -105,8 +108,8 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob jo
     const int q = u * C::LPB + g;
     const bool ok = q < total;
     const int qq = ok ? q : 0;
-    const int img = qq / job.nlines;          // lines of one image are ordered by column,
-    const int2 ln = job.lines[qq % job.nlines];  // so neighbouring lines share F[c]
+    const int img = qq / job.nlines;
+    const int2 ln = job.lines[qq % job.nlines];
     const int i = ln.x, c = ln.y;
     float2 v[V];
 #pragma unroll

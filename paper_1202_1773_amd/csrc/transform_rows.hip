@@ -49,6 +49,7 @@ struct RowJob {
   long long x_img_stride, z_img_stride, z_off_base;
   int nimg, nplanes, plane0, M, rb;   // rb = rows per block (divides M)
   int zp;                   // complex elements between consecutive columns of z (>= M)
+  int stream;               // k_r2c_rows: read x with non-temporal loads
   float inv_nplanes;
   Windows win;
   const float2* twN;        // exp(-2 pi i m / N), m < N
@@ -84,8 +85,13 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
     const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
     const float2* xr = reinterpret_cast<const float2*>(job.x + ru.img * job.x_img_stride +
                                                        ((long long)ru.plane * job.M + ru.r0 + (row_ok ? g : 0)) * N);
+    if (job.stream) {
 #pragma unroll
-    for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+      for (int s = 0; s < V; ++s) dst[s] = row_ok ? load_stream(xr + j + G * s) : make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+    }
   };
 
   float2 nxt[V];
@@ -246,8 +252,9 @@ static RowJob make_row_job(const RowArgs& a, int rb_max) {
   j.nplanes = a.nplanes;
   j.plane0 = a.plane0;
   j.M = a.M;
-  j.rb = rows_per_block(a.M, rb_max);
+  j.rb = rows_per_launch(a.M, rb_max, (long long)a.nimg * a.nplanes);
   j.zp = a.zp;
+  j.stream = (long long)a.nimg * a.nplanes * a.M * a.N * (long long)sizeof(float) > kStreamBytes;
   j.inv_nplanes = 1.0f / (float)a.nplanes;
   j.win = a.win;
   j.twN = a.twN;
