@@ -13,11 +13,12 @@ namespace ffst {
 __host__ __device__ constexpr int line_values(int L) {
   return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L >= 16 ? 16 : L);
 }
-// Column lines: 8 values per lane up to length 1024 (8*8*8 needs the same
-// two exchanges as 16*16*2 for 512, with far fewer registers), 16 above;
+// Column lines: 8 values per lane below length 1024 (8*8*8 needs the same
+// two exchanges as 16*16*2 for 512, with far fewer registers), 16 from 1024
+// on (one wave per line at 1024, measured faster than 8 values on two waves);
 // 12 for lengths 3 * 2^k.
 __host__ __device__ constexpr int col_values(int L) {
-  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L > 1024 ? 16 : (L >= 8 ? 8 : L));
+  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L >= 1024 ? 16 : (L >= 8 ? 8 : L));
 }
 
 // Rows per block that divide the image height: all M rows when M < rb_max,

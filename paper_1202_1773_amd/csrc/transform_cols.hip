@@ -10,10 +10,12 @@
 namespace ffst {
 namespace {
 
-// In-place FFT of nlines contiguous lines of length M. Inverse with nparts > 0:
-// each line is first replaced by the sum of the same line of `nparts`
-// partial arrays (parts + p * part_stride), added in order p = 0, 1, ...
-template <int M, bool INV>
+// In-place FFT of nlines contiguous lines of length M. PARTS (inverse with
+// nparts > 0): each line is first replaced by the sum of the same line of
+// `nparts` partial arrays (parts + p * part_stride), added in order
+// p = 0, 1, ...; a separate instantiation, so that the plain transform keeps
+// its registers.
+template <int M, bool INV, bool PARTS>
 __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines, int pitch,
                                                                   const float2* __restrict__ parts, int nparts,
                                                                   long long part_stride,
@@ -30,22 +32,27 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __rest
     const bool ok = line < nlines;
     float2* base = F + (long long)(ok ? line : 0) * pitch;
     float2 v[V];
-    if (nparts > 0) {
+    if constexpr (PARTS) {
 #pragma unroll
       for (int s = 0; s < V; ++s) v[s] = make_float2(0.f, 0.f);
-      // up to 8 partial arrays, all loads issued before the (fixed-order) sums
-      constexpr int MAXP = 8;
-      float2 t[MAXP][V];
+      // the partial arrays in groups of MAXP (64 values per lane in flight for
+      // 8-value lanes, fewer for wider lanes),
+      // every load of a group issued before its sums; sums in order p = 0, 1, ...
+      constexpr int MAXP = V <= 8 ? 8 : 2;
+      for (int p0 = 0; p0 < nparts; p0 += MAXP) {
+        float2 t[MAXP][V];
 #pragma unroll
-      for (int p = 0; p < MAXP; ++p) {
-        const float2* pb = parts + p * part_stride + (long long)(ok ? line : 0) * pitch;
+        for (int k = 0; k < MAXP; ++k) {
+          const int pk = p0 + k < nparts ? p0 + k : nparts - 1;   // in bounds even if loaded early
+          const float2* pb = parts + pk * part_stride + (long long)(ok ? line : 0) * pitch;
 #pragma unroll
-        for (int s = 0; s < V; ++s) t[p][s] = p < nparts ? pb[j + G * s] : make_float2(0.f, 0.f);
+          for (int s = 0; s < V; ++s) t[k][s] = p0 + k < nparts ? pb[j + G * s] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < MAXP; ++k)
+#pragma unroll
+          for (int s = 0; s < V; ++s) v[s] = cadd(v[s], t[k][s]);
       }
-#pragma unroll
-      for (int p = 0; p < MAXP; ++p)
-#pragma unroll
-        for (int s = 0; s < V; ++s) v[s] = cadd(v[s], t[p][s]);
     } else {
 #pragma unroll
       for (int s = 0; s < V; ++s) v[s] = base[j + G * s];
@@ -229,9 +236,9 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
   }
 }
 
-// For powers of two 64 <= M <= 1024 the body fits 128 registers (4 waves per
-// SIMD) with a few spills; other lengths (and the 12-value lanes of 3 * 2^k)
-// keep the compiler's own allocation.
+// For powers of two 64 <= M <= 512 the body fits 128 registers (4 waves per
+// SIMD) with a few spills; other lengths (16-value lanes from 1024 on, the
+// 12-value lanes of 3 * 2^k) keep the compiler's own allocation.
 template <int M, bool FUSED>
 __global__ void __launch_bounds__(LineCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_lines(AdjLineJob job) {
@@ -266,11 +273,14 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
   case n: {                                                                                       \
     const long long units = (nlines + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                     \
     const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if (inverse)                                                                                  \
-      hipLaunchKernelGGL((k_line_fft<n, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
+    if (inverse && nparts > 0)                                                                    \
+      hipLaunchKernelGGL((k_line_fft<n, true, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
+                         part_stride, twM);                                                       \
+    else if (inverse)                                                                             \
+      hipLaunchKernelGGL((k_line_fft<n, true, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
                          part_stride, twM);                                                       \
     else                                                                                          \
-      hipLaunchKernelGGL((k_line_fft<n, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
+      hipLaunchKernelGGL((k_line_fft<n, false, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
                          part_stride, twM);                                                       \
     return hipGetLastError();                                                                     \
   }
@@ -309,7 +319,7 @@ hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
   case n: {                                                                                       \
     const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
     const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if constexpr (n >= 64 && n <= 1024 && n % 3 != 0) {                                            \
+    if constexpr (n >= 64 && n <= 512 && n % 3 != 0) {                                             \
       if (a.fused)                                                                                \
         hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                       \
       else                                                                                        \
