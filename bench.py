@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--scales", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-images", type=int, default=3)
+    ap.add_argument("--cpu-images", type=int, default=6)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-batch and complex-shearlet measurements")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch settings only")
