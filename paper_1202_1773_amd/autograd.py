@@ -4,7 +4,10 @@ The forward transform is linear, c = SH f, so its vector-Jacobian product is
 the adjoint: d<g, SH f>/df = SH* g (Sec. 3.2-3.3: SH* is the inverse of the
 Parseval frame, eq. inverseShearletTransform). `ShearletTransform.backward`
 therefore calls the library's adjoint kernels; `ShearletAdjoint` is the
-mirror image (its backward is the forward transform).
+mirror image (its backward is the forward transform). With a complex-
+shearlet plan the coefficients are complex and the image real: torch hands
+the backward dL/dRe(c) + i dL/dIm(c), whose pull-back to the real image is
+Re SH^H g, exactly what the complex adjoint computes.
 
 `l1_denoise` runs plain (sub)gradient descent on
     L(x) = 1/2 ||x - y||^2 + lam ||SH x||_1

@@ -36,6 +36,23 @@ def test_backward_is_the_oracle_adjoint():
     plan.close()
 
 
+def test_backward_complex_shearlets():
+    # L = Re sum conj(W) c for complex W: the gradient is Re SH^H W, the
+    # oracle's real-part adjoint of the one-sided system
+    log("autograd backward, complex shearlets 64x64 J=2")
+    from oracle import complex_shearlets as ocs
+    plan = Plan(64, 64, 2, complex_shearlets=True)
+    rng = np.random.default_rng(23)
+    x = torch.from_numpy(rng.standard_normal((64, 64)).astype(np.float32)).to(DEV).requires_grad_(True)
+    w = (rng.standard_normal((13, 64, 64)) + 1j * rng.standard_normal((13, 64, 64))).astype(np.complex64)
+    c = shearlet_transform(x, plan)
+    loss = (torch.conj(torch.from_numpy(w).to(DEV)) * c).real.sum()
+    (g,) = torch.autograd.grad(loss, x)
+    ref = ocs.adjoint_real(w.astype(np.complex128), ocs.one_sided_spectra(64, 64, 2))
+    assert rel_l2(g.cpu().numpy(), ref) <= 1e-5
+    plan.close()
+
+
 def test_l1_gradient_matches_fp64_finite_differences():
     # 32x32 crops, J = 2 (13 spectra), lambda = 0.05, central differences with
     # h = 1e-6 on the FP64 oracle loss.
