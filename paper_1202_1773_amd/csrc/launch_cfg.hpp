@@ -56,6 +56,8 @@ struct RowCfg {
   static constexpr int RB = row_block_rows(G);
   static constexpr int THREADS = RB * G;
   static constexpr int STRIDE = lds_stride(L, V);
+  // groups must tile wavefronts exactly (wave-level sync, whole rows per block)
+  static_assert((G & (G - 1)) == 0, "lanes per row must be a power of two");
 };
 
 // Complex rows of length L (complex FFT of length L), RB rows per block.
@@ -67,6 +69,8 @@ struct CRowCfg {
   static constexpr int RB = row_block_rows(G);
   static constexpr int THREADS = RB * G;
   static constexpr int STRIDE = lds_stride(L, V);
+  // groups must tile wavefronts exactly (wave-level sync, whole rows per block)
+  static_assert((G & (G - 1)) == 0, "lanes per row must be a power of two");
 };
 
 // Contiguous lines of length L (the column direction, L = M).
@@ -78,6 +82,8 @@ struct LineCfg {
   static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
   static constexpr int LPB = THREADS / G;             // lines per block
   static constexpr int STRIDE = lds_stride(L, V);
+  // groups must tile wavefronts and the block exactly
+  static_assert((G & (G - 1)) == 0 && LPB * G == THREADS, "lanes per line must be a power of two");
 };
 
 // Compute units of the current device (read once per process).
