@@ -117,22 +117,35 @@ def test_batched_equals_separate_and_is_deterministic():
     plan.close()
 
 
-def test_bench_configuration_sampled():
+@pytest.mark.parametrize("tuned", [False, True])
+def test_bench_configuration_sampled(tuned):
     # The benchmark runs 16 images of 512x512, J = 3, in one call per
-    # direction; check sampled images against the oracle in that launch shape.
-    log("bench launch shape 16x512x512 J=3, sampled parity")
+    # direction (batched form) and the same images one per call (plain form),
+    # each plan autotuned first; check sampled images against the oracle in
+    # those launch shapes, with the built-in settings and after tuning.
+    log(f"bench launch shapes 16x512x512 J=3, sampled parity, tuned={tuned}")
     imgs = config2_batch(16)
     plan = Plan(512, 512, 3)
+    plan1 = Plan(512, 512, 3)
     x = torch.from_numpy(imgs).to(_dev())
+    if tuned:
+        plan.tune(x)
+        plan1.tune(x[0])
+        log(f"  settings batched {plan.tuning()}, plain {plan1.tuning()}")
     c = plan.forward(x)
     y = plan.adjoint(c)
     torch.cuda.synchronize()
     cn, yn = c.cpu().numpy(), y.cpu().numpy()
     for b in (0, 9, 15):
-        err = per_plane_rel_l2(cn[b], oracle_forward(imgs[b], 512, 512, 3))
+        ref = oracle_forward(imgs[b], 512, 512, 3)
+        err = per_plane_rel_l2(cn[b], ref)
         assert err.max() <= TOL
         assert rel_l2(yn[b], imgs[b]) <= TOL
+        c1 = plan1.forward(x[b])
+        assert per_plane_rel_l2(c1.cpu().numpy(), ref).max() <= TOL
+        assert rel_l2(plan1.adjoint(c1).cpu().numpy(), imgs[b]) <= TOL
     plan.close()
+    plan1.close()
 
 
 def test_large_2048_sampled_planes_and_properties():
