@@ -7,7 +7,8 @@
 //
 // Each stage is a radix-R Stockham autosort step, R being the largest
 // divisor of V that divides what is left of L (V, V, ..., then a smaller
-// power of two; with V = 12 for lengths 3 * 2^k: 12, 4, ..., 4, 2). A lane
+// power of two; with V = 12 for lengths 3 * 2^k: 12, 4, ..., 4, 2; with
+// V = 18 for lengths 9 * 2^k: 18, 2, ..., 2). A lane
 // runs V/R butterflies per
 // stage; butterfly b reads elements b + t*L/R, multiplies them by the twiddles
 // W_{pR}^{t (b mod p)} (p = product of the earlier radices), applies the
@@ -204,6 +205,69 @@ struct Dft<12, INV> {
   }
 };
 
+// cos and sin of 20, 40 and 80 degrees (the ninth and eighteenth roots of unity)
+constexpr float kCos20 = 0.93969262078590838405f, kSin20 = 0.34202014332566873304f;
+constexpr float kCos40 = 0.76604444311897803520f, kSin40 = 0.64278760968653932632f;
+constexpr float kCos80 = 0.17364817766693034885f, kSin80 = 0.98480775301220805936f;
+
+// 9 = 3 x 3: DFT3 over a[n2], a[n2+3], a[n2+6] for each n2, twiddles
+// exp(-+ 2 pi i n2 k1 / 9), then DFT3 over n2 giving outputs k1, k1+3, k1+6.
+template <bool INV>
+struct Dft<9, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    float2 t[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      t[n2][0] = a[n2];
+      t[n2][1] = a[n2 + 3];
+      t[n2][2] = a[n2 + 6];
+      Dft<3, INV>::run(t[n2]);
+    }
+    t[1][1] = cmul(t[1][1], make_float2(kCos40, sg * kSin40));   // w^1
+    t[1][2] = cmul(t[1][2], make_float2(kCos80, sg * kSin80));   // w^2
+    t[2][1] = cmul(t[2][1], make_float2(kCos80, sg * kSin80));   // w^2
+    t[2][2] = cmul(t[2][2], make_float2(-kCos20, sg * kSin20));  // w^4 (160 degrees)
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      float2 u[3] = {t[0][k1], t[1][k1], t[2][k1]};
+      Dft<3, INV>::run(u);
+      a[k1] = u[0];
+      a[k1 + 3] = u[1];
+      a[k1 + 6] = u[2];
+    }
+  }
+};
+
+// 18 = 2 x 9, twiddles exp(-+ 2 pi i k / 18) = exp(-+ i k 20 degrees).
+template <bool INV>
+struct Dft<18, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 e[9], o[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      e[k] = a[2 * k];
+      o[k] = a[2 * k + 1];
+    }
+    Dft<9, INV>::run(e);
+    Dft<9, INV>::run(o);
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    o[1] = cmul(o[1], make_float2(kCos20, sg * kSin20));
+    o[2] = cmul(o[2], make_float2(kCos40, sg * kSin40));
+    o[3] = cmul(o[3], make_float2(0.5f, sg * kSin60));
+    o[4] = cmul(o[4], make_float2(kCos80, sg * kSin80));
+    o[5] = cmul(o[5], make_float2(-kCos80, sg * kSin80));
+    o[6] = cmul(o[6], make_float2(-0.5f, sg * kSin60));
+    o[7] = cmul(o[7], make_float2(-kCos40, sg * kSin40));
+    o[8] = cmul(o[8], make_float2(-kCos20, sg * kSin20));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      a[k] = cadd(e[k], o[k]);
+      a[k + 9] = csub(e[k], o[k]);
+    }
+  }
+};
+
 // ----------------------------------------------------------- radix plan
 
 // Largest divisor of V that divides n.
@@ -267,7 +331,13 @@ struct TwiddleRegs {
       load_stage<S + 1>(j, table, ts);
     }
   }
+  // The lane index passes through an empty asm first, so the optimizer does
+  // not use its known range here: with that range (lane = threadIdx % G) the
+  // compiler of this toolchain produced wrong twiddles for length 144 with 18
+  // values per lane (measured on gfx950; the same code with threadIdx was
+  // correct). The load runs once per kernel.
   __device__ __forceinline__ void load(int j, const float2* __restrict__ table, int ts) {
+    __asm__ __volatile__("" : "+v"(j));
     load_stage<1>(j, table, ts);
   }
 };

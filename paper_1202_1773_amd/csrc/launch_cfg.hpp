@@ -8,17 +8,23 @@
 
 namespace ffst {
 
-// Values per lane. Lengths 3 * 2^k use 12 (radices 12, 4, ..., 2); powers
-// of two use 16 along rows.
+// Values per lane for lengths with a factor 3: 9 * 2^k use 18 (radices 18,
+// 2, ..., 2; 9 itself one radix-9 stage), 3 * 2^k use 12 (radices 12, 4, ...,
+// 2; 6 and 3 one stage).
+__host__ __device__ constexpr int values_with_three(int L) {
+  return L % 9 == 0 ? (L % 18 == 0 ? 18 : 9) : (L >= 12 ? 12 : L);
+}
+
+// Values per lane along rows: 16 for powers of two from 16 on.
 __host__ __device__ constexpr int line_values(int L) {
-  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L >= 16 ? 16 : L);
+  return L % 3 == 0 ? values_with_three(L) : (L >= 16 ? 16 : L);
 }
 // Column lines: 8 values per lane below length 1024 (8*8*8 needs the same
 // two exchanges as 16*16*2 for 512, with far fewer registers), 16 from 1024
 // on (one wave per line at 1024, measured faster than 8 values on two waves);
-// 12 for lengths 3 * 2^k.
+// lengths with a factor 3 as along rows.
 __host__ __device__ constexpr int col_values(int L) {
-  return L % 3 == 0 ? (L >= 12 ? 12 : L) : (L >= 1024 ? 16 : (L >= 8 ? 8 : L));
+  return L % 3 == 0 ? values_with_three(L) : (L >= 1024 ? 16 : (L >= 8 ? 8 : L));
 }
 
 // Rows per block that divide the image height: all M rows when M < rb_max,
@@ -123,11 +129,12 @@ __device__ __forceinline__ float2 load_stream(const float2* p) {
 // Reads above this size (about half the 256 MB Infinity Cache) use load_stream.
 constexpr long long kStreamBytes = 128LL << 20;
 
-// Rows per block for a launch of `rows_total` rows: the fixed block height,
-// halved (down to 4 rows) while the launch would have fewer blocks than CUs.
+// Rows per block for a launch over `units_of_planes` planes of M rows: the
+// fixed block height, halved (down to 4 rows, and only while the half still
+// divides M) while the launch would have fewer blocks than CUs.
 inline int rows_per_launch(int M, int rb_max, long long units_of_planes) {
   int rb = rows_per_block(M, rb_max);
-  while (rb > 4 && units_of_planes * (M / rb) < num_cus()) rb /= 2;
+  while (rb > 4 && rb % 2 == 0 && M % (rb / 2) == 0 && units_of_planes * (M / rb) < num_cus()) rb /= 2;
   return rb;
 }
 
