@@ -220,7 +220,9 @@ int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int ba
  * the graph, later calls with the same triple launch it. The workspace must
  * hold ffst_batch_workspace_size bytes (256-byte aligned); calls that run at
  * the same time need separate workspaces. ffst_batch_tune runs ffst_tune for
- * every class and drops the captured graphs; a graph captured before a class
+ * every class, keeps the new settings only if forward + adjoint of the whole
+ * batch got faster with them, and drops the captured graphs; a graph captured
+ * before a class
  * plan's settings were changed otherwise keeps the settings it was captured
  * with (its results are the same). ffst_batch_class returns a class's plan
  * (owned by the batch) and its image count.
