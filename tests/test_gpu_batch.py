@@ -160,8 +160,11 @@ def test_autotuner():
     bp = BatchPlan(SMALL, SMALL_J)
     f = bp.pack([torch.from_numpy(i) for i in imgs])
     bp.tune(f)
-    for n, b in bp.class_tuning():
-        assert 1 <= n <= 8
+    # the classes keep their tuned settings only if the whole batch got
+    # faster with them; otherwise every class is back at the defaults
+    tuned = bp.class_tuning()
+    log(f"  batch class settings {tuned}")
+    assert tuned == [(0, 0)] * bp.classes or all(1 <= n <= 8 and b in (0, 1, 2, 4, 8, 16) for n, b in tuned)
     y = bp.adjoint(bp.forward(f))
     for b, img in enumerate(bp.images(y)):
         assert rel_l2(img.cpu().numpy(), imgs[b]) <= TOL
