@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_c(CAdjLineJob
 
 // Complex row kernels take the full length N, line kernels the length M.
 // Powers of two, 3 * 2^k and 9 * 2^k.
-#define FFST_CROW_CASES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
+#define FFST_CROW_CASES(X) X(4) X(6) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
   X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)                             \
   X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304)
 #define FFST_CCOL_CASES(X) FFST_CROW_CASES(X)

@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
 
 // Row kernels take the complex length L = N/2: powers of two, 3 * 2^k and
 // 9 * 2^k.
-#define FFST_ROW_CASES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
+#define FFST_ROW_CASES(X) X(2) X(3) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
   X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536)                              \
   X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152)
 

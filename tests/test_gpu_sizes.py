@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
 TOL = 1e-5
 
-POW2 = [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
-THREE = [12, 24, 48, 96, 192, 384, 768, 1536, 3072]
+POW2 = [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
+THREE = [6, 12, 24, 48, 96, 192, 384, 768, 1536, 3072]
 NINE = [9, 18, 36, 72, 144, 288, 576, 1152, 2304]
 LENGTHS = POW2 + THREE + NINE
 
@@ -56,3 +56,12 @@ def test_every_length(L, complex_shearlets):
         err, rec = _check(M, N, J, complex_shearlets)
         log(f"  {M}x{N} J={J} complex={complex_shearlets}: fwd {err:.2e} rec {rec:.2e}")
         assert err <= TOL and rec <= TOL, (M, N)
+
+
+@pytest.mark.parametrize("complex_shearlets", [False, True])
+@pytest.mark.parametrize("M,N", [(4, 4), (6, 6), (4, 6), (6, 4), (4, 8), (12, 6), (9, 4)])
+def test_tiny_images(M, N, complex_shearlets):
+    # the smallest sides: J = 1 (5 spectra), every line a single FFT stage
+    err, rec = _check(M, N, 1, complex_shearlets)
+    log(f"  {M}x{N} J=1 complex={complex_shearlets}: fwd {err:.2e} rec {rec:.2e}")
+    assert err <= TOL and rec <= TOL, (M, N)
