@@ -47,8 +47,8 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_inv(CRowJob jo
   using C = CRowCfg<L>;
   constexpr int V = C::V, G = C::G, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
-  const int g = threadIdx.x / G;          // row slot (FFT phase)
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();          // row slot (FFT phase)
+  const int j = group_lane<C>();
   const int rb = job.rb;
   const int tr = threadIdx.x % rb;        // row (transpose phase)
   // first column (transpose phase); threads beyond rb * (NT / rb) sit out
@@ -109,8 +109,8 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
   using C = CRowCfg<L>;
   constexpr int V = C::V, G = C::G, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   const int rb = job.rb;
   const int tr = threadIdx.x % rb;
   const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
@@ -178,8 +178,8 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.nlines * job.nimg;
@@ -248,8 +248,8 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   float2* my = lds + g * C::STRIDE;
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
@@ -340,7 +340,9 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_c(CAdjLineJob
 // Powers of two, 3 * 2^k and 9 * 2^k.
 #define FFST_CROW_CASES(X) X(4) X(6) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
   X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)                             \
-  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304)
+  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304)                               \
+  X(27) X(54) X(108) X(216) X(432) X(864) X(1728) X(3456) X(81) X(162) X(324) X(648) X(1296) X(2592)  \
+  X(243) X(486) X(972) X(1944) X(3888) X(729) X(1458) X(2916) X(2187)
 #define FFST_CCOL_CASES(X) FFST_CROW_CASES(X)
 
 CRowJob make_crow_job(const CRowArgs& a, int rb_max) {

@@ -8,11 +8,18 @@
 
 namespace ffst {
 
-// Values per lane for lengths with a factor 3: 9 * 2^k use 18 (radices 18,
-// 2, ..., 2; 9 itself one radix-9 stage), 3 * 2^k use 12 (radices 12, 4, ...,
-// 2; 6 and 3 one stage).
+// Values per lane for lengths with a factor 3. 3 * 2^k use 12 (radices 12,
+// 4, ..., 2; 6 and 3 one stage). 9 * 2^k below 576 use 18 (radices 18, 2,
+// ..., 2; 9 itself one radix-9 stage); from 576 on the radix-2 stages of that
+// plan need more twiddle registers than a lane has, and 12 values (radices
+// 12, 12, 4 ...) take over. Lengths with 27 or a higher power of 3 use 12
+// when 4 divides them (radices 12, ..., then 6 or 3 for the remaining
+// threes), else 18 or 9 (then 9 and 3). With 12 values a group of 9 * 2^k or
+// 27 * 2^k lanes is not a power of two wide.
 __host__ __device__ constexpr int values_with_three(int L) {
-  return L % 9 == 0 ? (L % 18 == 0 ? 18 : 9) : (L >= 12 ? 12 : L);
+  return (L % 9 == 0 && L % 4 == 0 && (L % 27 == 0 || L >= 576)) ? 12
+         : L % 9 == 0 ? (L % 2 == 0 ? 18 : 9)
+                      : (L >= 12 ? 12 : L);
 }
 
 // Values per lane along rows: 16 for powers of two from 16 on.
@@ -45,12 +52,41 @@ __device__ __forceinline__ int mirror_index(int r, int L) { return r == 0 ? 0 : 
 // one row, both touch distinct banks.
 __host__ __device__ constexpr int lds_stride(int L, int V) { return stride_mod32(lds_group_len(L, V), 17); }
 
+__host__ __device__ constexpr int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (2 * p <= x) p *= 2;
+  return p;
+}
+
+// Lane slots of a group of G lanes. Groups of up to 64 lanes take the next
+// power of two of slots, so that groups tile wavefronts and exchange through
+// LDS with wave-level ordering only; wider groups (block barriers) take
+// exactly G. In a padded group the spare lanes act as copies of lane G - 1
+// (group_lane): the same loads, the same arithmetic, and the same values
+// stored to the same addresses in the same instructions.
+__host__ __device__ constexpr int group_slots(int G) { return G <= 64 ? pow2_ceil(G) : G; }
+
+template <class C>
+__device__ __forceinline__ int group_index() {
+  return threadIdx.x / C::GS;
+}
+template <class C>
+__device__ __forceinline__ int group_lane() {
+  const int j = threadIdx.x % C::GS;
+  return C::GS == C::G ? j : min(j, C::G - 1);
+}
+
 // Rows per block of the row kernels: 16 (128-byte column segments in the
 // transposed phase) while that keeps a block at <= 512 threads, whose 256
 // registers per lane hold a pipelined row FFT without spilling; longer rows
-// take fewer rows per block (512 / G).
-__host__ __device__ constexpr int row_block_rows(int G) {
-  return G <= 16 ? 256 / G : (G <= 32 ? 16 : 512 / G);
+// take fewer rows per block (512 / GS, rounded down to a power of two).
+__host__ __device__ constexpr int row_block_rows(int GS) {
+  return GS <= 16 ? 256 / GS : (GS <= 32 ? 16 : pow2_floor(512 / GS));
 }
 
 // Real rows of length N = 2L (complex FFT of length L), RB rows per block.
@@ -58,12 +94,14 @@ template <int L>
 struct RowCfg {
   static constexpr int V = line_values(L);
   static constexpr int G = L / V;                      // lanes per row
-  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int RB = row_block_rows(G);
-  static constexpr int THREADS = RB * G;
+  static constexpr int GS = group_slots(G);            // lane slots per row
+  static constexpr int SYNC = GS <= 64 ? kWave : kBlock;
+  static constexpr int RB = row_block_rows(GS);
+  static constexpr int THREADS = RB * GS;
   static constexpr int STRIDE = lds_stride(L, V);
-  // groups must tile wavefronts exactly (wave-level sync, whole rows per block)
-  static_assert((G & (G - 1)) == 0, "lanes per row must be a power of two");
+  // wave-level sync needs groups that tile wavefronts exactly
+  static_assert(SYNC == kBlock || (GS & (GS - 1)) == 0, "row slots must be a power of two");
+  static_assert(THREADS <= 1024, "row block too large");
 };
 
 // Complex rows of length L (complex FFT of length L), RB rows per block.
@@ -71,12 +109,13 @@ template <int L>
 struct CRowCfg {
   static constexpr int V = line_values(L);
   static constexpr int G = L / V;
-  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int RB = row_block_rows(G);
-  static constexpr int THREADS = RB * G;
+  static constexpr int GS = group_slots(G);
+  static constexpr int SYNC = GS <= 64 ? kWave : kBlock;
+  static constexpr int RB = row_block_rows(GS);
+  static constexpr int THREADS = RB * GS;
   static constexpr int STRIDE = lds_stride(L, V);
-  // groups must tile wavefronts exactly (wave-level sync, whole rows per block)
-  static_assert((G & (G - 1)) == 0, "lanes per row must be a power of two");
+  static_assert(SYNC == kBlock || (GS & (GS - 1)) == 0, "row slots must be a power of two");
+  static_assert(THREADS <= 1024, "row block too large");
 };
 
 // Contiguous lines of length L (the column direction, L = M).
@@ -84,12 +123,14 @@ template <int L>
 struct LineCfg {
   static constexpr int V = col_values(L);
   static constexpr int G = L / V;
-  static constexpr int SYNC = G <= 64 ? kWave : kBlock;
-  static constexpr int THREADS = G <= 64 ? 256 : G;   // kBlock: one line per block
-  static constexpr int LPB = THREADS / G;             // lines per block
+  static constexpr int GS = group_slots(G);
+  static constexpr int SYNC = GS <= 64 ? kWave : kBlock;
+  static constexpr int THREADS = GS <= 64 ? 256 : GS;  // kBlock: one line per block
+  static constexpr int LPB = THREADS / GS;             // lines per block
   static constexpr int STRIDE = lds_stride(L, V);
   // groups must tile wavefronts and the block exactly
-  static_assert((G & (G - 1)) == 0 && LPB * G == THREADS, "lanes per line must be a power of two");
+  static_assert((SYNC == kBlock || (GS & (GS - 1)) == 0) && LPB * GS == THREADS, "line slots must tile the block");
+  static_assert(THREADS <= 1024, "line block too large");
 };
 
 // Compute units of the current device (read once per process).

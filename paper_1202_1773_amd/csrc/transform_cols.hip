@@ -23,8 +23,8 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __rest
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   TwiddleRegs<M, V> tw;
   tw.load(j, twM, 1);
   for (int u = blockIdx.x; u * C::LPB < nlines; u += gridDim.x) {
@@ -84,8 +84,8 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob jo
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.nlines * job.nimg;
@@ -155,8 +155,8 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   float2* my = lds + g * C::STRIDE;
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
@@ -250,10 +250,12 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_wide(AdjLineJ
   adj_lines_body<M, FUSED>(job);
 }
 
-// Line kernels take the length M: powers of two, 3 * 2^k and 9 * 2^k.
+// Line kernels take the length M: every 2^a 3^b from 4 to 4096.
 #define FFST_COL_CASES(X) X(4) X(6) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
   X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)                             \
-  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304)
+  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304)                               \
+  X(27) X(54) X(108) X(216) X(432) X(864) X(1728) X(3456) X(81) X(162) X(324) X(648) X(1296) X(2592)  \
+  X(243) X(486) X(972) X(1944) X(3888) X(729) X(1458) X(2916) X(2187)
 
 }  // namespace
 

@@ -65,8 +65,8 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
   using C = RowCfg<L>;
   constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
-  const int g = threadIdx.x / G;          // row slot (FFT phase)
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();          // row slot (FFT phase)
+  const int j = group_lane<C>();
   const int rb = SMALL ? job.rb : C::RB;
   const int tr = threadIdx.x % rb;        // row (transpose phase)
   // first column (transpose phase); with a runtime rb that does not divide
@@ -134,8 +134,8 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
   constexpr int NLD = L / STEP + 1;
   __shared__ float2 lds[C::RB * C::STRIDE];
   __shared__ float2 wsh[L];               // W_N^k, k < L
-  const int g = threadIdx.x / G;
-  const int j = threadIdx.x % G;
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
   const int rb = SMALL ? job.rb : C::RB;
   const int tr = threadIdx.x % rb;
   const int tc = (!SMALL || threadIdx.x < rb * (NT / rb)) ? threadIdx.x / rb : (1 << 29);
@@ -225,11 +225,12 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
   }
 }
 
-// Row kernels take the complex length L = N/2: powers of two, 3 * 2^k and
-// 9 * 2^k.
+// Row kernels take the complex length L = N/2: every 2^a 3^b from 2 to 2048.
 #define FFST_ROW_CASES(X) X(2) X(3) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
   X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536)                              \
-  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152)
+  X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152)                                   \
+  X(27) X(54) X(108) X(216) X(432) X(864) X(1728) X(81) X(162) X(324) X(648) X(1296) X(243) X(486)    \
+  X(972) X(1944) X(729) X(1458)
 
 }  // namespace
 

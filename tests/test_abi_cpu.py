@@ -47,7 +47,8 @@ def test_spectra_rejects_bad_arguments(lib):
     # valid transform sizes that this GPU path does not run
     assert lib.ffst_spectra(320, 512, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(512, 6144, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
-    assert lib.ffst_spectra(512, 54, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(512, 50, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(4374, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(512, 9, 1, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(63, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(8192, 8192, 0, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED

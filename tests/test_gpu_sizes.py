@@ -19,28 +19,34 @@ TOL = 1e-5
 POW2 = [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
 THREE = [6, 12, 24, 48, 96, 192, 384, 768, 1536, 3072]
 NINE = [9, 18, 36, 72, 144, 288, 576, 1152, 2304]
-LENGTHS = POW2 + THREE + NINE
+# 27 and higher powers of 3: groups that are not a power of two lanes wide
+HIGHER = [27, 54, 108, 216, 432, 864, 1728, 3456, 81, 162, 324, 648, 1296, 2592,
+          243, 486, 972, 1944, 3888, 729, 1458, 2916, 2187]
+LENGTHS = POW2 + THREE + NINE + HIGHER
 
 
-def _check(M, N, J, complex_shearlets):
-    f = gaussian(M, N, seed=M * 7 + N)
-    x = torch.from_numpy(f).to(DEV)
+def _check(M, N, J, complex_shearlets, batch=1):
+    fs = [gaussian(M, N, seed=M * 7 + N + b) for b in range(batch)]
+    x = torch.from_numpy(np.stack(fs)).to(DEV)
     plan = Plan(M, N, J, complex_shearlets=complex_shearlets)
     c = plan.forward(x)
-    if complex_shearlets:
-        pp = ocs.one_sided_spectra(M, N, J)
-        ref = ocs.forward(f.astype(np.float64), pp)
-        got = c.cpu().numpy()
-        num = np.sqrt((np.abs(got - ref) ** 2).sum(axis=(-2, -1)))
-        den = np.sqrt((np.abs(ref) ** 2).sum(axis=(-2, -1)))
-        big = den > 1e-12 * np.linalg.norm(f)
-        err = float((num[big] / den[big]).max())
-    else:
-        ref = oracle_forward(f, M, N, J)
-        den = np.sqrt((ref ** 2).sum(axis=(-2, -1)))
-        big = den > 1e-12 * np.linalg.norm(f)
-        err = float(per_plane_rel_l2(c.cpu().numpy()[big], ref[big]).max())
-    rec = rel_l2(plan.adjoint(c).cpu().numpy(), f)
+    y = plan.adjoint(c).cpu().numpy()
+    err = rec = 0.0
+    for b, f in enumerate(fs):
+        if complex_shearlets:
+            pp = ocs.one_sided_spectra(M, N, J)
+            ref = ocs.forward(f.astype(np.float64), pp)
+            got = c[b].cpu().numpy()
+            num = np.sqrt((np.abs(got - ref) ** 2).sum(axis=(-2, -1)))
+            den = np.sqrt((np.abs(ref) ** 2).sum(axis=(-2, -1)))
+            big = den > 1e-12 * np.linalg.norm(f)
+            err = max(err, float((num[big] / den[big]).max()))
+        else:
+            ref = oracle_forward(f, M, N, J)
+            den = np.sqrt((ref ** 2).sum(axis=(-2, -1)))
+            big = den > 1e-12 * np.linalg.norm(f)
+            err = max(err, float(per_plane_rel_l2(c[b].cpu().numpy()[big], ref[big]).max()))
+        rec = max(rec, rel_l2(y[b], f))
     plan.close()
     return err, rec
 
@@ -64,4 +70,13 @@ def test_tiny_images(M, N, complex_shearlets):
     # the smallest sides: J = 1 (5 spectra), every line a single FFT stage
     err, rec = _check(M, N, 1, complex_shearlets)
     log(f"  {M}x{N} J=1 complex={complex_shearlets}: fwd {err:.2e} rec {rec:.2e}")
+    assert err <= TOL and rec <= TOL, (M, N)
+
+
+@pytest.mark.parametrize("complex_shearlets", [False, True])
+@pytest.mark.parametrize("M,N,J", [(216, 216, 3), (324, 162, 3), (243, 486, 3), (108, 864, 3), (81, 54, 2)])
+def test_higher_powers_of_three(M, N, J, complex_shearlets):
+    # both sides with 27 or more as a factor, two images per call
+    err, rec = _check(M, N, J, complex_shearlets, batch=2)
+    log(f"  {M}x{N} J={J} complex={complex_shearlets} batch 2: fwd {err:.2e} rec {rec:.2e}")
     assert err <= TOL and rec <= TOL, (M, N)
