@@ -26,8 +26,7 @@
  *                                               columns 0 .. N/2 of each plane,
  *                                               the rest follows from evenness
  *
- * Supported on the GPU: M and N of the form 2^a 3^b in [4, 4096], N even;
- * 1 <= J <= 10.
+ * Supported on the GPU: M and N of the form 2^a 3^b in [4, 4096]; 1 <= J <= 10.
  *
  * Ownership: the plan owns the spectra and its tables and frees them in
  * ffst_destroy. The caller owns f, coeffs and the workspace ws (device memory

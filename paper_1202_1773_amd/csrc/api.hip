@@ -393,7 +393,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
   if (!supported_length(M) || !supported_length(N) || !supported_row_length(N))
     return fail(FFST_EUNSUPPORTED,
-                "GPU path supports sides 2^a 3^b in [4, 4096], N even (got %d x %d)", M, N);
+                "GPU path supports sides 2^a 3^b in [4, 4096] (got %d x %d)", M, N);
 
   ffst_plan* p = new (std::nothrow) ffst_plan();
   if (!p) return fail(FFST_ENOMEM, "host allocation failed");

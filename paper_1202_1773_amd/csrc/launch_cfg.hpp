@@ -167,6 +167,8 @@ __device__ __forceinline__ float2 load_stream(const float2* p) {
   return v;
 }
 
+__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
+
 // Reads above this size (about half the 256 MB Infinity Cache) use load_stream.
 constexpr long long kStreamBytes = 128LL << 20;
 

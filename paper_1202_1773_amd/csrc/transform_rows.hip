@@ -225,6 +225,129 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
   }
 }
 
+// Odd row lengths N (no half-length packing): a complex FFT of length N per
+// row. Forward: x[n] + 0i, X = FFT_N, keep X[c] for the window columns
+// (c <= (N-1)/2). Inverse: the window columns give X[c] for c <= (N-1)/2,
+// X[N-c] = conj X[c] completes the Hermitian row, and the real part of the
+// unnormalised inverse FFT_N is the row (the same scaling as k_c2r_rows).
+template <int N>
+__global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job) {
+  using C = CRowCfg<N>;
+  constexpr int V = C::V, G = C::G, NT = C::THREADS;
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
+  const int rb = job.rb;
+  const int tr = threadIdx.x % rb;
+  // threads beyond rb * (NT / rb) sit out of the transposed store
+  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
+  const int cstep = NT / rb;
+  const bool row_ok = g < rb;
+  float2* my = lds + g * C::STRIDE;
+  const float2* zr = lds + tr * C::STRIDE;
+  TwiddleRegs<N, V> tw;
+  tw.load(j, job.twN, 1);
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+
+  auto load_rows = [&](int u, float2 (&dst)[V]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const float* xr = job.x + ru.img * job.x_img_stride + ((long long)ru.plane * job.M + ru.r0 + (row_ok ? g : 0)) * N;
+    if (job.stream) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s] = make_float2(row_ok ? load_stream(xr + j + G * s) : 0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s] = make_float2(row_ok ? xr[j + G * s] : 0.f, 0.f);
+    }
+  };
+
+  float2 nxt[V];
+  int u = blockIdx.x;
+  if (u < nunits) load_rows(u, nxt);
+  for (; u < nunits; u += gridDim.x) {
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = nxt[s];
+    if (u + (int)gridDim.x < nunits) load_rows(u + gridDim.x, nxt);
+    fft_group<N, V, false, C::SYNC>(v, j, my, tw);
+#pragma unroll
+    for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = v[s];
+    __syncthreads();
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    float2* out = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+#pragma unroll 4
+    for (int m = tc; m < w; m += cstep) out[(long long)m * job.zp] = zr[lpad<V>(lo + m)];
+    __syncthreads();
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_c2r_rows_odd(RowJob job) {
+  using C = CRowCfg<N>;
+  constexpr int V = C::V, G = C::G, NT = C::THREADS;
+  constexpr int H = N / 2 + 1;                       // stored columns 0 .. (N-1)/2
+  constexpr int NH = (H + C::GS - 1) / C::GS;        // loads per thread (cstep >= GS)
+  __shared__ float2 lds[C::RB * C::STRIDE];
+  const int g = group_index<C>();
+  const int j = group_lane<C>();
+  const int rb = job.rb;
+  const int tr = threadIdx.x % rb;
+  const int tc = threadIdx.x < rb * (NT / rb) ? threadIdx.x / rb : (1 << 29);
+  const int cstep = NT / rb;
+  const bool row_ok = g < rb;
+  float2* my = lds + g * C::STRIDE;
+  float2* zr = lds + tr * C::STRIDE;
+  TwiddleRegs<N, V> tw;
+  tw.load(j, job.twN, 1);
+  const int bpp = job.M / rb;
+  const int nunits = job.nimg * job.nplanes * bpp;
+
+  // columns k = tc + cstep * m of row tr, k < H (zero outside the window)
+  auto load_cols = [&](int u, float2 (&dst)[NH]) {
+    const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+    const int lo = job.win.lo[ru.plane], w = job.win.w[ru.plane];
+    const float2* in = job.z + ru.img * job.z_img_stride + (job.win.off[ru.plane] - job.z_off_base) + ru.r0 + tr;
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+      const int k = tc + cstep * m;
+      dst[m] = (k < H && (unsigned)(k - lo) < (unsigned)w) ? in[(long long)(k - lo) * job.zp] : make_float2(0.f, 0.f);
+    }
+  };
+
+  float2 nxt[NH];
+  int u = blockIdx.x;
+  if (u < nunits) load_cols(u, nxt);
+  for (; u < nunits; u += gridDim.x) {
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+      const int k = tc + cstep * m;
+      if (k < H) {
+        zr[lpad<V>(k)] = nxt[m];
+        if (k > 0) zr[lpad<V>(N - k)] = conjf2(nxt[m]);
+      }
+    }
+    __syncthreads();
+    if (u + (int)gridDim.x < nunits) load_cols(u + gridDim.x, nxt);
+    float2 v[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) v[s] = my[lpad<V>(j + G * s)];
+    lds_sync<C::SYNC>();
+    fft_group<N, V, true, C::SYNC>(v, j, my, tw);
+    if (row_ok) {
+      const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
+      float* yr = job.x + ru.img * job.x_img_stride + ((long long)ru.plane * job.M + ru.r0 + g) * N;
+#pragma unroll
+      for (int s = 0; s < V; ++s) yr[j + G * s] = v[s].x;
+    }
+    __syncthreads();
+  }
+}
+
+// Odd row lengths: the odd 3^b from 9 to 2187.
+#define FFST_ODD_ROW_CASES(X) X(9) X(27) X(81) X(243) X(729) X(2187)
+
 // Row kernels take the complex length L = N/2: every 2^a 3^b from 2 to 2048.
 #define FFST_ROW_CASES(X) X(2) X(3) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
   X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536)                              \
@@ -235,7 +358,14 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
 }  // namespace
 
 bool supported_row_length(int N) {
-  if (N % 2) return false;
+  if (N % 2) {
+    switch (N) {
+#define CASE(n) case n: return true;
+      FFST_ODD_ROW_CASES(CASE)
+#undef CASE
+      default: return false;
+    }
+  }
   switch (N / 2) {
 #define CASE(n) case n: return true;
     FFST_ROW_CASES(CASE)
@@ -264,8 +394,28 @@ static RowJob make_row_job(const RowArgs& a, int rb_max) {
   return j;
 }
 
+static hipError_t launch_rows_odd(const RowArgs& a, bool inverse, hipStream_t s) {
+  switch (a.N) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    const RowJob job = make_row_job(a, CRowCfg<n>::RB);                                           \
+    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
+    const dim3 grid(grid_for(units, CRowCfg<n>::THREADS)), block(CRowCfg<n>::THREADS);           \
+    if (inverse)                                                                                  \
+      hipLaunchKernelGGL(k_c2r_rows_odd<n>, grid, block, 0, s, job);                              \
+    else                                                                                          \
+      hipLaunchKernelGGL(k_r2c_rows_odd<n>, grid, block, 0, s, job);                              \
+    return hipGetLastError();                                                                     \
+  }
+    FFST_ODD_ROW_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s) {
   if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  if (a.N % 2) return launch_rows_odd(a, false, s);
   switch (a.N / 2) {
 #define CASE(n)                                                                                   \
   case n: {                                                                                       \
@@ -286,6 +436,7 @@ hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s) {
 
 hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s) {
   if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
+  if (a.N % 2) return launch_rows_odd(a, true, s);
   switch (a.N / 2) {
 #define CASE(n)                                                                                   \
   case n: {                                                                                       \

@@ -49,7 +49,7 @@ def test_spectra_rejects_bad_arguments(lib):
     assert lib.ffst_spectra(512, 6144, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(512, 50, 3, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(4374, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
-    assert lib.ffst_spectra(512, 9, 1, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
+    assert lib.ffst_spectra(512, 15, 1, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(63, 64, 2, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     assert lib.ffst_spectra(8192, 8192, 0, ctypes.byref(out)) == _lib.FFST_EUNSUPPORTED
     bad = _lib.ffst_options(2, 0)

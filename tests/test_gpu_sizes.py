@@ -1,6 +1,7 @@
 """Every FFT length the library is compiled for, once as the column length M
-and once as the row length N (real and complex shearlets), against the FP64
-oracle: each kernel instantiation runs at least once with its own data."""
+and once as the row length N (odd N through the odd-row kernels), with real
+and complex shearlets, against the FP64 oracle: each kernel instantiation
+runs at least once with its own data."""
 
 import numpy as np
 import pytest
@@ -54,9 +55,7 @@ def _check(M, N, J, complex_shearlets, batch=1):
 @pytest.mark.parametrize("complex_shearlets", [False, True])
 @pytest.mark.parametrize("L", LENGTHS)
 def test_every_length(L, complex_shearlets):
-    cases = [(L, 64)]
-    if L % 2 == 0:
-        cases.append((32, L))
+    cases = [(L, 64), (32, L)]
     for M, N in cases:
         J = min(2, (max(M, N).bit_length() - 1) // 2)
         err, rec = _check(M, N, J, complex_shearlets)
@@ -65,7 +64,7 @@ def test_every_length(L, complex_shearlets):
 
 
 @pytest.mark.parametrize("complex_shearlets", [False, True])
-@pytest.mark.parametrize("M,N", [(4, 4), (6, 6), (4, 6), (6, 4), (4, 8), (12, 6), (9, 4)])
+@pytest.mark.parametrize("M,N", [(4, 4), (6, 6), (4, 6), (6, 4), (4, 8), (12, 6), (9, 4), (9, 9), (4, 9)])
 def test_tiny_images(M, N, complex_shearlets):
     # the smallest sides: J = 1 (5 spectra), every line a single FFT stage
     err, rec = _check(M, N, 1, complex_shearlets)
@@ -74,7 +73,8 @@ def test_tiny_images(M, N, complex_shearlets):
 
 
 @pytest.mark.parametrize("complex_shearlets", [False, True])
-@pytest.mark.parametrize("M,N,J", [(216, 216, 3), (324, 162, 3), (243, 486, 3), (108, 864, 3), (81, 54, 2)])
+@pytest.mark.parametrize("M,N,J", [(216, 216, 3), (324, 162, 3), (243, 486, 3), (108, 864, 3), (81, 54, 2),
+                                   (27, 81, 2), (96, 243, 3), (243, 729, 3)])
 def test_higher_powers_of_three(M, N, J, complex_shearlets):
     # both sides with 27 or more as a factor, two images per call
     err, rec = _check(M, N, J, complex_shearlets, batch=2)
