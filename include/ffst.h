@@ -207,7 +207,8 @@ int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int ba
  * scales (J[b] <= 0: the default for that size) and the options shared by all
  * of them (NULL = defaults). Images of the same (M, N, J) form a class and
  * share one plan. The batch packs every class contiguously, classes in the
- * order of their first image, images of a class in the given order:
+ * order of their first image, each class block starting on a 256-byte
+ * boundary (unused floats in between), images of a class in the given order:
  * ffst_batch_layout writes, per image b (host arrays of count entries), the
  * float offset of its image in the packed image buffer and of its
  * coefficients ([eta_b][M_b][N_b], real or complex as the options say) in the

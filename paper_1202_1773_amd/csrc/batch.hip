@@ -238,14 +238,17 @@ int ffst_batch_create(int count, const int* M, const int* N, const int* J, const
   b->cls_ws_size.resize(nc);
   long long io = 0, co = 0;
   size_t wo = 0;
+  // class blocks start on 256-byte boundaries (64 floats): images of odd
+  // size would otherwise leave the next class misaligned for its plan
+  auto align64 = [](long long x) { return (x + 63) & ~63LL; };
   for (size_t c = 0; c < nc; ++c) {
     int m = 0, n = 0;
     plan_size(b->plans[c], &m, &n);
     const long long mn = (long long)m * n;
     b->cls_img_off[c] = io;
     b->cls_coef_off[c] = co;
-    io += mn * b->cls_images[c];
-    co += cmul * plan_eta(b->plans[c]) * mn * b->cls_images[c];
+    io = align64(io + mn * b->cls_images[c]);
+    co = align64(co + cmul * plan_eta(b->plans[c]) * mn * b->cls_images[c]);
     b->cls_ws_off[c] = wo;
     b->cls_ws_size[c] = align256(workspace_upper_bound(b->plans[c], b->cls_images[c]));
     wo += b->cls_ws_size[c];

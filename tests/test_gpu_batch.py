@@ -110,6 +110,25 @@ def test_complex_uneven_batch():
     bp.close()
 
 
+def test_uneven_batch_odd_and_27_sides():
+    log("uneven batch with odd widths and sides with a factor 27")
+    sizes = [(27, 54), (81, 9), (27, 54), (243, 64), (9, 9), (108, 81)]
+    Js = [2, 2, 2, 3, 1, 3]
+    imgs = [cartoon(m, n, 8, 3, 0.1, seed=980 + b) for b, (m, n) in enumerate(sizes)]
+    bp = BatchPlan(sizes, Js)
+    assert bp.classes == 5
+    f = bp.pack([torch.from_numpy(i) for i in imgs])
+    c = bp.forward(f)
+    views = bp.coefficients(c)
+    for b, (M, N) in enumerate(sizes):
+        err = per_plane_rel_l2(views[b].cpu().numpy(), oracle_forward(imgs[b], M, N, Js[b]))
+        assert err.max() <= TOL, (b, err.max())
+    y = bp.adjoint(c)
+    for b, img in enumerate(bp.images(y)):
+        assert rel_l2(img.cpu().numpy(), imgs[b]) <= TOL, b
+    bp.close()
+
+
 def test_uneven_workload_64_images():
     # the uneven workload: 64 images drawn from 256^2 .. 1024^2 (seed 401),
     # J = 3 up to 512, else 4; one image per size checked on sampled planes,
