@@ -36,6 +36,13 @@
  * host and never allocate. f and coeffs must not overlap; ws must not overlap
  * either. Two calls that run concurrently need separate workspaces.
  *
+ * Threads: transform calls do not modify the plan, so several host threads
+ * may call them at once, on one plan or on several, each with its own
+ * workspace (and normally its own stream). Creating, tuning and destroying a
+ * plan, ffst_set_tuning and the batch calls on one batch must not run
+ * concurrently with other calls on the same object. While kernel timing
+ * (ffst_profile_*) is enabled, all calls must come from one thread.
+ *
  * Errors: every function returns an ffst_status. Arguments are checked
  * before any device work; on failure nothing is launched and nothing is
  * written. ffst_last_error() returns a message for the last failure of the

@@ -4,6 +4,7 @@
 #include "launch_cfg.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -83,8 +84,10 @@ struct ProfRec {
   int id;
   hipEvent_t a, b;
 };
-unsigned g_mask = 0;
-bool g_profile_suspended = false;       // set while a graph is being captured
+// Read by every transform call, on any thread: atomics (relaxed; the
+// timing records themselves are not thread-safe).
+std::atomic<unsigned> g_mask{0};
+std::atomic<bool> g_profile_suspended{false};  // set while a graph is being captured
 std::vector<ProfRec> g_recs;
 std::vector<hipEvent_t> g_pool;  // events reused across timed launches
 double g_total_ms[KID_COUNT] = {};
@@ -103,7 +106,8 @@ hipEvent_t pooled_event() {
 
 template <class Fn>
 hipError_t timed(int id, hipStream_t s, Fn&& fn) {
-  if (g_profile_suspended || !((g_mask >> id) & 1u)) return fn();
+  if (g_profile_suspended.load(std::memory_order_relaxed) || !((g_mask.load(std::memory_order_relaxed) >> id) & 1u))
+    return fn();
   ProfRec r{id, pooled_event(), pooled_event()};
   if (!r.a || !r.b) return fn();
   (void)hipEventRecord(r.a, s);
@@ -357,7 +361,7 @@ Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_
 
 }  // namespace
 
-void ffst::profile_suspend(bool on) { g_profile_suspended = on; }
+void ffst::profile_suspend(bool on) { g_profile_suspended.store(on, std::memory_order_relaxed); }
 
 size_t ffst::workspace_upper_bound(const ffst_plan* p, int batch) {
   if (!plan_ok(p) || batch <= 0) return 0;
@@ -865,7 +869,7 @@ void ffst_destroy(ffst_plan* p) {
 const char* ffst_last_error(void) { return g_err.c_str(); }
 
 int ffst_profile_enable(unsigned mask) {
-  g_mask = mask;
+  g_mask.store(mask, std::memory_order_relaxed);
   return FFST_OK;
 }
 

@@ -133,16 +133,17 @@ struct LineCfg {
   static_assert(THREADS <= 1024, "line block too large");
 };
 
-// Compute units of the current device (read once per process).
+// Compute units of the current device (read once per process; the static's
+// initialisation is thread-safe).
 inline int num_cus() {
-  static int n = 0;
-  if (n == 0) {
+  static const int n = [] {
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      n = prop.multiProcessorCount;
-    if (n <= 0) n = 256;
-  }
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+      return prop.multiProcessorCount;
+    return 256;
+  }();
   return n;
 }
 
