@@ -14,6 +14,9 @@ Prints ONE JSON line:
                the current kernel sources, else null
   path_roofline  the whole step's algorithmic bytes over the step time
   cpu_baseline the FP64 CPU oracle on a bounded sample (1 thread)
+  cpu_library  context only: the same transform on the same sample with
+               scipy.fft on every host core and the plan's spectra, in
+               float64 and float32
   complex_shearlets  the same images with complex (one-sided) shearlets
   uneven_batch the 64-image uneven batch (256^2 .. 1024^2, seed 401) through
                one HIP graph launch per direction, with the built-in launch
@@ -89,6 +92,44 @@ def cpu_baseline(M, N, J, images):
     return {"value": coef / dt / 1e9, "unit": "Gcoef/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(images)} image(s) of {M}x{N}, J={J}: forward+adjoint, FP64 NumPy, "
                       f"{dt:.1f} s on {cpu_model()} (os.cpu_count()={os.cpu_count()})"}
+
+
+def library_transform(x, p, M, N, workers):
+    """Forward coefficients and adjoint images of the images x [B][M][N] with
+    scipy.fft and half-plane spectra p [eta][M][N/2+1]."""
+    import scipy.fft as sf
+
+    F = sf.rfft2(x, workers=workers)
+    c = sf.irfft2(F[:, None] * p[None], s=(M, N), workers=workers)
+    A = (sf.rfft2(c, workers=workers) * p[None]).sum(axis=1)
+    return c, sf.irfft2(A, s=(M, N), workers=workers)
+
+
+def cpu_library(psi, images, M, N, reps=3):
+    """Context only: the same forward + adjoint with a library CPU FFT
+    (scipy.fft rfft2 / irfft2 on every host core), given the half-plane
+    spectra psi [eta][M][N/2+1], in float64 and in float32; best of `reps`.
+    fft2 unnormalised and 1/(MN) in ifft2, as in the transform's definition."""
+    import numpy as np
+
+    workers = os.cpu_count() or 1
+    eta = psi.shape[0]
+    x64 = np.stack(images).astype(np.float64)
+    out = {"unit": "Gcoef/s", "cores": workers, "kind": "library (scipy.fft, same spectra)"}
+    for name, dt in (("f64", np.float64), ("f32", np.float32)):
+        x = x64.astype(dt)
+        p = psi.astype(dt)
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, y = library_transform(x, p, M, N, workers)
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        out[name] = len(images) * eta * M * N / best / 1e9
+        out[name + "_reconstruction_rel_l2"] = float(np.linalg.norm(y - x64) / np.linalg.norm(x64))
+    out["sample"] = (f"{len(images)} image(s) of {M}x{N}, {eta} spectra: forward+adjoint, best of {reps}, "
+                     f"{workers} threads on {cpu_model()}")
+    return out
 
 
 def nnz_half(plan):
@@ -388,13 +429,16 @@ def main():
         out["uneven_batch"] = bench_uneven(extra_steps, 2, not args.no_tune)
         out["large_image"] = bench_large(extra_steps, 2, not args.no_tune)
 
+    psi_half = plan.spectra(full_plane=False).cpu().numpy() if not args.no_cpu_baseline else None
     plan.close()
     plan1.close()
     del c, y, x
     torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(M, N, J, [imgs[i] for i in range(min(args.cpu_images, B))])
+        sample = [imgs[i] for i in range(min(args.cpu_images, B))]
+        out["cpu_baseline"] = cpu_baseline(M, N, J, sample)
+        out["cpu_library"] = cpu_library(psi_half, sample, M, N)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
