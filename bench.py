@@ -365,6 +365,8 @@ def main():
     coef_bytes = 4 * coef_per_step
     img_bytes = 4 * B * M * N
     b_alg = 2 * coef_bytes + 2 * img_bytes + 2 * 4 * nnz_half
+    b_dense = 2 * coef_bytes + 2 * img_bytes + 2 * 4 * eta * M * (N // 2 + 1)
+    b_floor = 2 * coef_bytes + 2 * img_bytes
     kernel_alg = {
         "k_c2r_rows(planes)": coef_bytes,     # coefficients written
         "k_r2c_rows(planes)": coef_bytes,     # coefficients read
@@ -408,7 +410,13 @@ def main():
                           "achieved": round(b_alg / (ms_step * 1e-3) / 1e9, 2),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(b_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          "nnz_half_spectra": nnz_half},
+                          "nnz_half_spectra": nnz_half,
+                          # the same with the spectra read densely (eta * M * (N/2+1)
+                          # values per direction), and without them (the floor)
+                          "dense_half_bytes_per_step": b_dense,
+                          "dense_half_frac": round(b_dense / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "floor_bytes_per_step": b_floor,
+                          "floor_frac": round(b_floor / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms_per_step": {k: round(v[0], 5) for k, v in per_kernel.items()},
         "check": {"reconstruction_rel_l2": rec_err},
         "source_sha": source_sha(),
