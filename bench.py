@@ -22,6 +22,10 @@ Prints ONE JSON line:
                one HIP graph launch per direction, with the built-in launch
                settings and after the autotuner
   large_image  one 2048 x 2048 image, J = 5 (125 spectra)
+  smooth_shearlets  the headline images with smooth shearlets
+  l1_denoise   one step of l1 denoising by gradient descent (forward
+               transform, gradient through the adjoint kernels, update) on
+               16 noisy 512 x 512 images
 The batched and plain plans are autotuned (launch settings only) before any
 timing unless --no-tune is given.
 
@@ -216,6 +220,63 @@ def bench_complex(x, M, N, J, steps, warmup):
     return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
             "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
             "reconstruction_rel_l2": rec}
+
+
+def bench_smooth(x, M, N, J, steps, warmup):
+    """Smooth shearlets (Sec. 3.4) on the headline images: forward + adjoint per
+    step; the same kernels with other spectra."""
+    import torch
+    from paper_1202_1773_amd import Plan
+
+    plan = Plan(M, N, J, shearlet="smooth")
+    B = x.shape[0]
+    c = torch.empty((B, plan.eta, M, N), dtype=torch.float32, device=x.device)
+    y = torch.empty_like(x)
+
+    def step():
+        plan.forward(x, out=c)
+        plan.adjoint(c, out=y)
+
+    t = time_steps(step, steps, warmup)
+    coef = B * plan.eta * M * N
+    b_alg = 4 * (2 * coef + 2 * B * M * N + 2 * nnz_half(plan))
+    rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+    plan.close()
+    return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
+            "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
+            "reconstruction_rel_l2": rec}
+
+
+def bench_denoise(steps, warmup):
+    """l1 denoising by gradient descent through the differentiable transform:
+    16 images 512 x 512, J = 3, y = cartoon + N(0, 0.1^2) (seeds 301..316),
+    lambda = 0.05; one step = loss (forward transform) + gradient (adjoint
+    kernels through autograd) + update."""
+    import numpy as np
+    import torch
+    from paper_1202_1773_amd import Plan
+    from paper_1202_1773_amd.autograd import l1_loss
+    from paper_1202_1773_amd.synthetic import cartoon
+
+    M = N = 512
+    plan = Plan(M, N, 3)
+    yimg = torch.from_numpy(np.stack([cartoon(M, N, 20, 10, 0.1, seed=301 + b) for b in range(16)])).to("cuda")
+    x = yimg.clone().requires_grad_(True)
+    losses = []
+
+    def step():
+        loss = l1_loss(x, yimg, plan, 0.05)
+        (g,) = torch.autograd.grad(loss, x)
+        with torch.no_grad():
+            x.sub_(0.25 * g)
+        losses.append(loss.detach())
+
+    t = time_steps(step, steps, warmup)
+    coef = 16 * plan.eta * M * N
+    first, last = float(losses[0]), float(losses[-1])
+    plan.close()
+    return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
+            "lambda": 0.05, "loss_first": first, "loss_last": last}
 
 
 def bench_large(steps, warmup, tune):
@@ -436,6 +497,8 @@ def main():
         out["complex_shearlets"] = bench_complex(x, M, N, J, extra_steps, 2)
         out["uneven_batch"] = bench_uneven(extra_steps, 2, not args.no_tune)
         out["large_image"] = bench_large(extra_steps, 2, not args.no_tune)
+        out["smooth_shearlets"] = bench_smooth(x, M, N, J, extra_steps, 2)
+        out["l1_denoise"] = bench_denoise(extra_steps, 2)
 
     psi_half = plan.spectra(full_plane=False).cpu().numpy() if not args.no_cpu_baseline else None
     plan.close()

@@ -50,8 +50,10 @@ def shearlet_adjoint(c, plan):
 
 
 def l1_loss(x, y, plan, lam):
-    """1/2 ||x - y||^2 + lam ||SH x||_1, summed over the batch."""
-    return 0.5 * ((x - y) ** 2).sum() + lam * shearlet_transform(x, plan).abs().sum()
+    """1/2 ||x - y||^2 + lam ||SH x||_1, summed over the batch. The l1 norm is
+    one reduction over the coefficients (no |c| temporary); its gradient is
+    lam * sign(c), pulled back by the adjoint kernels."""
+    return 0.5 * ((x - y) ** 2).sum() + lam * torch.linalg.vector_norm(shearlet_transform(x, plan), ord=1)
 
 
 def l1_denoise(y, plan, lam=0.05, steps=200, lr=0.5, x0=None):
