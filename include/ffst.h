@@ -143,6 +143,29 @@ int ffst_plan_windows(const ffst_plan* plan, int* first_col, int* last_col);
  * last_col, so last_col < first_col when the range wraps past N - 1. */
 
 /*
+ * Index order of the coefficient planes (Sec. 3.5.2; what the paper's toolbox
+ * helper computes between the index i and scale / shear): plane 0 is the
+ * low-pass; scale j (0 .. J-1) follows with 2^(j+2) planes, counter-clockwise:
+ * horizontal cone k = 0, -1, .., -2^j+1, the seam element k = -2^j, vertical
+ * cone k = -2^j+1 .. 2^j-1, the seam element k = 2^j, horizontal cone
+ * k = 2^j-1 .. 1. The dilation and shear of plane (j, k) are a = 4^-j and
+ * s = k 2^-j. Pure functions of J (1 <= J <= 10); no plan or GPU needed.
+ *
+ * ffst_scale_shear writes the kind, j and k of plane i (0 <= i < eta; the
+ * low-pass has j = -1, k = 0). ffst_shearlet_index writes the index of
+ * (kind, j, k) (for the low-pass j and k are ignored); FFST_EINVAL for a
+ * combination that does not occur.
+ */
+typedef enum {
+    FFST_KIND_LOWPASS = 0,
+    FFST_KIND_HORIZONTAL = 1,
+    FFST_KIND_VERTICAL = 2,
+    FFST_KIND_SEAM = 3     /* glued horizontal/vertical element, k = +-2^j */
+} ffst_kind;
+int ffst_scale_shear(int J, int i, int* kind, int* j, int* k);
+int ffst_shearlet_index(int J, int kind, int j, int k, int* i);
+
+/*
  * Forward transform of `batch` images: coeffs[b][i] = ifft2(Psi_i .* fft2(f[b])).
  * batch = 0 is a no-op. Asynchronous on `stream`.
  */

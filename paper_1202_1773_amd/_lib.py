@@ -19,10 +19,18 @@ FFST_EBADPLAN = 5
 FFST_SHEARLET_MEYER = 0
 FFST_SHEARLET_MEYER_SMOOTH = 1
 
+FFST_KIND_LOWPASS = 0
+FFST_KIND_HORIZONTAL = 1
+FFST_KIND_VERTICAL = 2
+FFST_KIND_SEAM = 3
+KIND_NAMES = {FFST_KIND_LOWPASS: "lowpass", FFST_KIND_HORIZONTAL: "horizontal", FFST_KIND_VERTICAL: "vertical",
+              FFST_KIND_SEAM: "seam"}
+
 EXPORTED = [
     "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
     "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
     "ffst_inverse", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
+    "ffst_scale_shear", "ffst_shearlet_index",
     "ffst_set_tuning", "ffst_get_tuning", "ffst_tune",
     "ffst_batch_create", "ffst_batch_info", "ffst_batch_class", "ffst_batch_layout",
     "ffst_batch_workspace_size", "ffst_batch_forward", "ffst_batch_adjoint", "ffst_batch_inverse",
@@ -70,6 +78,8 @@ def load():
         "ffst_forward_complex": (I, [P, P, P, I, P, P]),
         "ffst_adjoint_complex": (I, [P, P, P, I, P, P]),
         "ffst_inverse_complex": (I, [P, P, P, I, P, P]),
+        "ffst_scale_shear": (I, [I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_shearlet_index": (I, [I, I, I, I, ctypes.POINTER(I)]),
         "ffst_set_tuning": (I, [P, I, I]),
         "ffst_get_tuning": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "ffst_tune": (I, [P, P, P, P, I, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double)]),
@@ -137,6 +147,21 @@ def ffst_plan_info(plan):
 
 def ffst_workspace_size(plan, batch):
     return int(load().ffst_workspace_size(plan, int(batch)))
+
+
+def ffst_scale_shear(J, i):
+    """(kind, j, k) of coefficient plane i of a J-scale transform."""
+    kind, j, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().ffst_scale_shear(int(J), int(i), ctypes.byref(kind), ctypes.byref(j), ctypes.byref(k)),
+           "ffst_scale_shear")
+    return kind.value, j.value, k.value
+
+
+def ffst_shearlet_index(J, kind, j, k):
+    """Index of the plane (kind, j, k) of a J-scale transform."""
+    i = ctypes.c_int()
+    _check(load().ffst_shearlet_index(int(J), int(kind), int(j), int(k), ctypes.byref(i)), "ffst_shearlet_index")
+    return i.value
 
 
 def ffst_get_spectra(plan, dst_ptr, full_plane=0):

@@ -599,6 +599,36 @@ int ffst_plan_windows(const ffst_plan* p, int* first_col, int* last_col) {
   return ok();
 }
 
+static_assert(FFST_KIND_LOWPASS == KIND_LOWPASS && FFST_KIND_HORIZONTAL == KIND_H && FFST_KIND_VERTICAL == KIND_V &&
+                  FFST_KIND_SEAM == KIND_SEAM,
+              "public and internal spectrum kinds must agree");
+
+int ffst_scale_shear(int J, int i, int* kind, int* j, int* k) {
+  if (!kind || !j || !k) return fail(FFST_EINVAL, "ffst_scale_shear: outputs must be non-NULL");
+  if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
+  const int eta = (1 << (J + 2)) - 3;
+  if (i < 0 || i >= eta) return fail(FFST_EINVAL, "index %d outside [0, %d)", i, eta);
+  std::vector<int> kd, jj, kk;
+  index_order(J, kd, jj, kk);
+  *kind = kd[i];
+  *j = kd[i] == KIND_LOWPASS ? -1 : jj[i];
+  *k = kk[i];
+  return ok();
+}
+
+int ffst_shearlet_index(int J, int kind, int j, int k, int* i) {
+  if (!i) return fail(FFST_EINVAL, "ffst_shearlet_index: output must be non-NULL");
+  if (J < 1 || J > 10) return fail(FFST_EINVAL, "number of scales must be in [1, 10] (got %d)", J);
+  std::vector<int> kd, jj, kk;
+  index_order(J, kd, jj, kk);
+  for (size_t t = 0; t < kd.size(); ++t)
+    if (kd[t] == kind && (kind == KIND_LOWPASS || (jj[t] == j && kk[t] == k))) {
+      *i = (int)t;
+      return ok();
+    }
+  return fail(FFST_EINVAL, "no plane of kind %d with j = %d, k = %d for J = %d", kind, j, k, J);
+}
+
 int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, false, "ffst_forward") != FFST_OK) return FFST_EINVAL;

@@ -130,6 +130,18 @@ class Plan:
         _lib.ffst_get_spectra(self._h, dst.data_ptr(), 1 if full_plane else 0)
         return dst
 
+    def scale_shear(self, i):
+        """('lowpass' | 'horizontal' | 'vertical' | 'seam', j, k) of plane i;
+        its dilation and shear are a = 4^-j and s = k 2^-j (j = -1 for the
+        low-pass)."""
+        kind, j, k = _lib.ffst_scale_shear(self.J, i)
+        return _lib.KIND_NAMES[kind], j, k
+
+    def index(self, kind, j=0, k=0):
+        """Plane index of (kind, j, k), kind as returned by scale_shear."""
+        code = {v: c for c, v in _lib.KIND_NAMES.items()}[kind]
+        return _lib.ffst_shearlet_index(self.J, code, j, k)
+
     def windows(self):
         """Per spectrum, the first and last column holding a nonzero (half
         plane; for a complex plan a cyclic range of full-plane columns)."""
