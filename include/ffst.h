@@ -184,6 +184,19 @@ int ffst_inverse(const ffst_plan* plan, const float* coeffs, float* f, int batch
                  void* ws, void* stream);
 
 /*
+ * Adjoint of the l1 subgradient (the gradient step of an l1 penalty on the
+ * coefficients, Sec. 3.3 adjoint applied to s * sign(c)): f[b] = SH*(s *
+ * sign(coeffs[b])) with sign(0) = 0, computed by ffst_adjoint's kernels with
+ * the sign applied as the coefficients are read (no pass over them before).
+ * `scale` points to ONE float s in device memory, read when the kernels run
+ * (so a gradient scale computed on the device needs no host round trip).
+ * Real-shearlet plans only (FFST_EINVAL otherwise); layouts, workspace and
+ * errors as ffst_adjoint.
+ */
+int ffst_adjoint_sign(const ffst_plan* plan, const float* coeffs, float* f, int batch, const float* scale,
+                      void* ws, void* stream);
+
+/*
  * Complex shearlets (Sec. 3.8.2), on a plan created with complex_shearlets = 1.
  * Coefficients are complex, stored as interleaved float pairs (re, im):
  * coeffs [batch][eta][M][N][2], 8-byte aligned; the images stay real.

@@ -29,7 +29,7 @@ KIND_NAMES = {FFST_KIND_LOWPASS: "lowpass", FFST_KIND_HORIZONTAL: "horizontal", 
 EXPORTED = [
     "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
     "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
-    "ffst_inverse", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
+    "ffst_inverse", "ffst_adjoint_sign", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
     "ffst_scale_shear", "ffst_shearlet_index",
     "ffst_set_tuning", "ffst_get_tuning", "ffst_tune",
     "ffst_batch_create", "ffst_batch_info", "ffst_batch_class", "ffst_batch_layout",
@@ -75,6 +75,7 @@ def load():
         "ffst_forward": (I, [P, P, P, I, P, P]),
         "ffst_adjoint": (I, [P, P, P, I, P, P]),
         "ffst_inverse": (I, [P, P, P, I, P, P]),
+        "ffst_adjoint_sign": (I, [P, P, P, I, P, P, P]),
         "ffst_forward_complex": (I, [P, P, P, I, P, P]),
         "ffst_adjoint_complex": (I, [P, P, P, I, P, P]),
         "ffst_inverse_complex": (I, [P, P, P, I, P, P]),
@@ -183,6 +184,12 @@ def ffst_forward(plan, f_ptr, c_ptr, batch, ws_ptr, stream_ptr):
 def ffst_adjoint(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):
     _check(load().ffst_adjoint(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
                                ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_adjoint")
+
+
+def ffst_adjoint_sign(plan, c_ptr, f_ptr, batch, scale_ptr, ws_ptr, stream_ptr):
+    _check(load().ffst_adjoint_sign(plan, ctypes.c_void_p(c_ptr), ctypes.c_void_p(f_ptr), int(batch),
+                                    ctypes.c_void_p(scale_ptr), ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)),
+           "ffst_adjoint_sign")
 
 
 def ffst_inverse(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):

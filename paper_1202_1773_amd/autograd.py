@@ -11,7 +11,9 @@ Re SH^H g, exactly what the complex adjoint computes.
 
 `l1_denoise` runs plain (sub)gradient descent on
     L(x) = 1/2 ||x - y||^2 + lam ||SH x||_1
-with the gradient from autograd, i.e. from the adjoint kernels.
+with the gradient from autograd, i.e. from the adjoint kernels; for real
+shearlets the subgradient lam * sign(SH x) is applied inside the adjoint
+kernels (`ShearletL1`).
 """
 
 import torch
@@ -49,11 +51,38 @@ def shearlet_adjoint(c, plan):
     return ShearletAdjoint.apply(c, plan)
 
 
+class ShearletL1(torch.autograd.Function):
+    """lam * ||SH x||_1 for a real-shearlet plan. Backward: SH*(lam g sign(c))
+    in one call of the adjoint kernels, which apply the sign as they read the
+    coefficients (the scale lam * g stays on the device)."""
+
+    @staticmethod
+    def forward(ctx, x, plan, lam):
+        c = plan.forward(x.contiguous())
+        ctx.plan, ctx.lam = plan, lam
+        ctx.save_for_backward(c)
+        return lam * torch.linalg.vector_norm(c, ord=1)
+
+    @staticmethod
+    def backward(ctx, g):
+        (c,) = ctx.saved_tensors
+        scale = (g * ctx.lam).reshape(1).to(torch.float32).contiguous()
+        return ctx.plan.adjoint_sign(c, scale), None, None
+
+
+def shearlet_l1(x, plan, lam):
+    """lam * ||SH x||_1 (the modulus of complex coefficients for a
+    complex-shearlet plan), differentiable in x."""
+    if plan.complex_shearlets:
+        return lam * torch.linalg.vector_norm(shearlet_transform(x, plan), ord=1)
+    return ShearletL1.apply(x, plan, lam)
+
+
 def l1_loss(x, y, plan, lam):
     """1/2 ||x - y||^2 + lam ||SH x||_1, summed over the batch. The l1 norm is
-    one reduction over the coefficients (no |c| temporary); its gradient is
-    lam * sign(c), pulled back by the adjoint kernels."""
-    return 0.5 * ((x - y) ** 2).sum() + lam * torch.linalg.vector_norm(shearlet_transform(x, plan), ord=1)
+    one reduction over the coefficients; its gradient lam * sign(c) is pulled
+    back by the adjoint kernels without being stored."""
+    return 0.5 * ((x - y) ** 2).sum() + shearlet_l1(x, plan, lam)
 
 
 def l1_denoise(y, plan, lam=0.05, steps=200, lr=0.5, x0=None):

@@ -672,9 +672,14 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   return launched(e, "ffst_forward");
 }
 
-int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+namespace {
+
+// The real adjoint; with sign_scale (a device scalar s) the coefficients are
+// read as s * sign(c).
+int adjoint_real(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream,
+                 const float* sign_scale, const char* what) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
-  if (reject_kind(p, false, "ffst_adjoint") != FFST_OK) return FFST_EINVAL;
+  if (reject_kind(p, false, what) != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
   int st = check_call(p, coeffs, img * p->eta * (size_t)std::max(batch, 0), f, img * (size_t)std::max(batch, 0),
                       batch, ws);
@@ -697,7 +702,7 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
       RowArgs rr{const_cast<float*>(coeffs) + img0 * p->eta * MN, Z, p->eta * MN, unit_stride, base, nimg,
-                 p1 - p0, p0, p->M, p->N, p->pitch, plane_windows(p), p->twN};
+                 p1 - p0, p0, p->M, p->N, p->pitch, plane_windows(p), p->twN, sign_scale};
       e = timed(KID_R2C_PLANES, s, [&] { return launch_r2c_rows(rr, s); });
       if (e != hipSuccess) break;
       AdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psi,
@@ -715,7 +720,19 @@ int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, v
     RowArgs rc{f, A, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
     e = timed(KID_C2R_IMAGE, s, [&] { return launch_c2r_rows(rc, s); });
   }
-  return launched(e, "ffst_adjoint");
+  return launched(e, what);
+}
+
+}  // namespace
+
+int ffst_adjoint(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  return adjoint_real(p, coeffs, f, batch, ws, stream, nullptr, "ffst_adjoint");
+}
+
+int ffst_adjoint_sign(const ffst_plan* p, const float* coeffs, float* f, int batch, const float* scale, void* ws,
+                      void* stream) {
+  if (!scale) return fail(FFST_EINVAL, "ffst_adjoint_sign: scale must be a non-NULL device pointer");
+  return adjoint_real(p, coeffs, f, batch, ws, stream, scale, "ffst_adjoint_sign");
 }
 
 int ffst_inverse(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {

@@ -72,6 +72,7 @@ struct RowArgs {
   int zp;                   // complex elements between consecutive columns of z
   Windows win;
   const float2* twN;
+  const float* sign_scale = nullptr;   // r2c only: read s * sign(x) (device scalar s)
 };
 hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s);
 hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s);

@@ -53,15 +53,25 @@ struct RowJob {
   float inv_nplanes;
   Windows win;
   const float2* twN;        // exp(-2 pi i m / N), m < N
+  const float* sign_scale;  // k_r2c_rows_sign: device scalar s; row value x read as s * sign(x)
 };
+
+// s * sign(x), sign(0) = 0
+__device__ __forceinline__ float sign_times(float x, float s) { return x > 0.f ? s : (x < 0.f ? -s : 0.f); }
+__device__ __forceinline__ float2 sign_times(float2 v, float s) {
+  return make_float2(sign_times(v.x, s), sign_times(v.y, s));
+}
 
 // SMALL: images with fewer than RB rows; the block then covers job.rb rows.
 //
 // Both row kernels are software-pipelined over the units a block visits: the
 // global loads of the next unit are issued before the current unit's FFT, so
 // their latency overlaps the arithmetic.
-template <int L, bool SMALL>
-__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
+//
+// SIGN (k_r2c_rows_sign): the rows are read as s * sign(x), the subgradient of
+// s * ||x||_1, so that the adjoint of an l1 term needs no extra pass.
+template <int L, bool SMALL, bool SIGN>
+__device__ __forceinline__ void r2c_rows_body(const RowJob& job) {
   using C = RowCfg<L>;
   constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
@@ -80,6 +90,8 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
   tw.load(j, job.twN, 2);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
+  float sgs = 0.f;
+  if constexpr (SIGN) sgs = *job.sign_scale;
 
   auto load_rows = [&](int u, float2 (&dst)[V]) {
     const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
@@ -91,6 +103,10 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
     } else {
 #pragma unroll
       for (int s = 0; s < V; ++s) dst[s] = row_ok ? xr[j + G * s] : make_float2(0.f, 0.f);
+    }
+    if constexpr (SIGN) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s] = sign_times(dst[s], sgs);
     }
   };
 
@@ -123,6 +139,16 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
     }
     __syncthreads();
   }
+}
+
+template <int L, bool SMALL>
+__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
+  r2c_rows_body<L, SMALL, false>(job);
+}
+
+template <int L, bool SMALL>
+__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows_sign(RowJob job) {
+  r2c_rows_body<L, SMALL, true>(job);
 }
 
 template <int L, bool SMALL>
@@ -230,8 +256,8 @@ __global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
 // (c <= (N-1)/2). Inverse: the window columns give X[c] for c <= (N-1)/2,
 // X[N-c] = conj X[c] completes the Hermitian row, and the real part of the
 // unnormalised inverse FFT_N is the row (the same scaling as k_c2r_rows).
-template <int N>
-__global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job) {
+template <int N, bool SIGN>
+__device__ __forceinline__ void r2c_rows_odd_body(const RowJob& job) {
   using C = CRowCfg<N>;
   constexpr int V = C::V, G = C::G, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
@@ -249,6 +275,8 @@ __global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job
   tw.load(j, job.twN, 1);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
+  float sgs = 0.f;
+  if constexpr (SIGN) sgs = *job.sign_scale;
 
   auto load_rows = [&](int u, float2 (&dst)[V]) {
     const RowUnit ru = row_unit(u, bpp, job.nplanes, job.inv_nplanes, rb, job.plane0);
@@ -259,6 +287,10 @@ __global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job
     } else {
 #pragma unroll
       for (int s = 0; s < V; ++s) dst[s] = make_float2(row_ok ? xr[j + G * s] : 0.f, 0.f);
+    }
+    if constexpr (SIGN) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) dst[s].x = sign_times(dst[s].x, sgs);
     }
   };
 
@@ -281,6 +313,16 @@ __global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job
     for (int m = tc; m < w; m += cstep) out[(long long)m * job.zp] = zr[lpad<V>(lo + m)];
     __syncthreads();
   }
+}
+
+template <int N>
+__global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd(RowJob job) {
+  r2c_rows_odd_body<N, false>(job);
+}
+
+template <int N>
+__global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_r2c_rows_odd_sign(RowJob job) {
+  r2c_rows_odd_body<N, true>(job);
 }
 
 template <int N>
@@ -391,6 +433,7 @@ static RowJob make_row_job(const RowArgs& a, int rb_max) {
   j.inv_nplanes = 1.0f / (float)a.nplanes;
   j.win = a.win;
   j.twN = a.twN;
+  j.sign_scale = a.sign_scale;
   return j;
 }
 
@@ -403,6 +446,8 @@ static hipError_t launch_rows_odd(const RowArgs& a, bool inverse, hipStream_t s)
     const dim3 grid(grid_for(units, CRowCfg<n>::THREADS)), block(CRowCfg<n>::THREADS);           \
     if (inverse)                                                                                  \
       hipLaunchKernelGGL(k_c2r_rows_odd<n>, grid, block, 0, s, job);                              \
+    else if (job.sign_scale)                                                                      \
+      hipLaunchKernelGGL(k_r2c_rows_odd_sign<n>, grid, block, 0, s, job);                         \
     else                                                                                          \
       hipLaunchKernelGGL(k_r2c_rows_odd<n>, grid, block, 0, s, job);                              \
     return hipGetLastError();                                                                     \
@@ -422,7 +467,11 @@ hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s) {
     const RowJob job = make_row_job(a, RowCfg<n>::RB);                                            \
     const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
     const dim3 grid(grid_for(units, RowCfg<n>::THREADS)), block(RowCfg<n>::THREADS);             \
-    if (job.rb < RowCfg<n>::RB)                                                                   \
+    if (job.sign_scale && job.rb < RowCfg<n>::RB)                                                 \
+      hipLaunchKernelGGL((k_r2c_rows_sign<n, true>), grid, block, 0, s, job);                         \
+    else if (job.sign_scale)                                                                      \
+      hipLaunchKernelGGL((k_r2c_rows_sign<n, false>), grid, block, 0, s, job);                        \
+    else if (job.rb < RowCfg<n>::RB)                                                              \
       hipLaunchKernelGGL((k_r2c_rows<n, true>), grid, block, 0, s, job);                              \
     else                                                                                          \
       hipLaunchKernelGGL((k_r2c_rows<n, false>), grid, block, 0, s, job);                             \

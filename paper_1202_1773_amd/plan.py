@@ -90,6 +90,28 @@ class Plan:
         call(self._h, cb.data_ptr(), out.data_ptr(), B, ws if ws is not None else self.workspace(B), self._stream())
         return out.reshape(self.M, self.N) if single else out.reshape(B, self.M, self.N)
 
+    def adjoint_sign(self, c, scale, out=None, ws=None):
+        """SH*(scale * sign(c)) for a real-shearlet plan; scale is a one-element
+        float32 tensor on the plan's device (read by the kernels)."""
+        if self.complex_shearlets:
+            raise ValueError("adjoint_sign is for real-shearlet plans")
+        self._check(c, (self.eta, self.M, self.N))
+        if not (isinstance(scale, torch.Tensor) and scale.device == self.device and scale.dtype == torch.float32
+                and scale.numel() == 1):
+            raise ValueError("scale must be a one-element float32 tensor on the plan's device")
+        single = c.dim() == 3
+        cb = c.reshape(-1, self.eta, self.M, self.N)
+        B = cb.shape[0]
+        if out is None:
+            out = torch.empty((B, self.M, self.N), dtype=torch.float32, device=self.device)
+        self._check(out, (self.M, self.N))
+        if out.numel() != B * self.M * self.N:
+            raise ValueError("output has the wrong number of elements")
+        sc = scale.contiguous()
+        _lib.ffst_adjoint_sign(self._h, cb.data_ptr(), out.data_ptr(), B, sc.data_ptr(),
+                               ws if ws is not None else self.workspace(B), self._stream())
+        return out.reshape(self.M, self.N) if single else out.reshape(B, self.M, self.N)
+
     def inverse(self, c, out=None, ws=None):
         return self.adjoint(c, out=out, ws=ws)
 
