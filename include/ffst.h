@@ -260,7 +260,9 @@ int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int ba
  * A transform call runs every class on a stream of its own, forked from and
  * joined back into `stream`, and is replayed as one HIP graph: the first call
  * with a given (input, output, workspace) triple captures and instantiates
- * the graph, later calls with the same triple launch it. The workspace must
+ * the graph, later calls with the same triple launch it (the graphs of the
+ * eight most recently used triples per direction are kept; callers that want
+ * every call to be a replay pass the same buffers each time). The workspace must
  * hold ffst_batch_workspace_size bytes (256-byte aligned); calls that run at
  * the same time need separate workspaces. ffst_batch_tune runs ffst_tune for
  * every class, keeps the new settings only if forward + adjoint of the whole
@@ -289,6 +291,26 @@ void ffst_destroy(ffst_plan* plan);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* ffst_last_error(void);
+
+/*
+ * Identifier of the sources this library was compiled from: a hash of the
+ * kernel and host sources, this header and the compiler flags, fixed at build
+ * time (a static string owned by the library). Bindings compare it with the
+ * hash of the sources they ship with and refuse a library built from others.
+ */
+const char* ffst_build_id(void);
+
+/*
+ * Bytes of device memory currently held by the plans and batches of this
+ * process (spectra, tables; workspaces belong to the caller and are not
+ * counted). A leak check for error paths: plan or batch creation that fails
+ * releases everything it allocated, so the count returns to its earlier
+ * value. Test hook: with the environment variable FFST_FAULT_ALLOC=n (n >= 1),
+ * the n-th device allocation inside one ffst_spectra / ffst_spectra_ex /
+ * ffst_batch_create call fails as if the device were out of memory, and the
+ * call returns FFST_ENOMEM after releasing what it had allocated.
+ */
+size_t ffst_device_bytes(void);
 
 /*
  * Kernel timing. With profiling enabled, every launch of a kernel whose id

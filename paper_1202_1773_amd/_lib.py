@@ -7,7 +7,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libffst.so")
+# FFST_LIBRARY may name another build of the same sources (the host-sanitizer
+# build libffst_asan.so); its build id is checked like the default library's.
+LIB_PATH = os.environ.get("FFST_LIBRARY") or os.path.join(HERE, "libffst.so")
 
 FFST_OK = 0
 FFST_EINVAL = 1
@@ -35,7 +37,7 @@ EXPORTED = [
     "ffst_batch_create", "ffst_batch_info", "ffst_batch_class", "ffst_batch_layout",
     "ffst_batch_workspace_size", "ffst_batch_forward", "ffst_batch_adjoint", "ffst_batch_inverse",
     "ffst_batch_tune", "ffst_batch_destroy",
-    "ffst_destroy", "ffst_last_error", "ffst_profile_enable",
+    "ffst_destroy", "ffst_last_error", "ffst_build_id", "ffst_device_bytes", "ffst_profile_enable",
     "ffst_profile_read", "ffst_profile_reset", "ffst_num_kernels", "ffst_kernel_name",
 ]
 
@@ -54,15 +56,28 @@ class ffst_options(ctypes.Structure):
 _lib = None
 
 
+def check_build_id(lib_id, tree_id):
+    """Refuse a library whose compiled-in build id differs from the hash of
+    the sources next to it (a stale or foreign libffst.so)."""
+    if lib_id != tree_id:
+        raise ImportError(f"{LIB_PATH} was built from other sources (library build id {lib_id}, "
+                          f"sources {tree_id}): rebuild with `python -m paper_1202_1773_amd.build`")
+
+
 def load():
-    """Load libffst.so (built in-tree by paper_1202_1773_amd.build)."""
+    """Load libffst.so (built in-tree by paper_1202_1773_amd.build) after
+    checking that it was built from the sources in this tree."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1202_1773_amd.build` (there is no fallback path)")
+    from .build import build_id
     lib = ctypes.CDLL(LIB_PATH)
+    lib.ffst_build_id.restype = ctypes.c_char_p
+    lib.ffst_build_id.argtypes = []
+    check_build_id(lib.ffst_build_id().decode(), build_id())
     P = ctypes.c_void_p
     I = ctypes.c_int
     sig = {
@@ -98,6 +113,8 @@ def load():
         "ffst_batch_destroy": (None, [P]),
         "ffst_destroy": (None, [P]),
         "ffst_last_error": (ctypes.c_char_p, []),
+        "ffst_build_id": (ctypes.c_char_p, []),
+        "ffst_device_bytes": (ctypes.c_size_t, []),
         "ffst_profile_enable": (I, [ctypes.c_uint]),
         "ffst_profile_read": (I, [I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
         "ffst_profile_reset": (I, []),
@@ -301,6 +318,14 @@ def ffst_destroy(plan):
 
 def ffst_last_error():
     return load().ffst_last_error().decode()
+
+
+def ffst_build_id():
+    return load().ffst_build_id().decode()
+
+
+def ffst_device_bytes():
+    return int(load().ffst_device_bytes())
 
 
 def ffst_profile_enable(mask):

@@ -21,7 +21,9 @@ class BatchPlan:
     contiguous): pack() / images() / coefficients() move between the packed
     buffers and per-image views. forward / adjoint take and return packed
     buffers; the first call with a given (input, output, workspace) triple
-    captures a HIP graph that later calls replay.
+    captures a HIP graph that later calls replay (the library keeps the
+    graphs of the eight most recent triples per direction). Pass `out`
+    buffers that persist across calls to make every call a replay.
     """
 
     def __init__(self, sizes, J=None, max_scale="max", shearlet="meyer", complex_shearlets=False, aux=3,

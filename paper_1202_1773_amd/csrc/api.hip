@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace ffst;
@@ -63,6 +65,60 @@ int ffst::fail(int status, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return status;
+}
+
+// ---- device memory held by plans and batches ---------------------------
+//
+// Every device allocation of the library goes through dev_alloc / dev_free,
+// which keep the bytes held (ffst_device_bytes) and let a test make the n-th
+// allocation of one plan or batch creation fail: with FFST_FAULT_ALLOC=n in
+// the environment, the n-th dev_alloc inside one ffst_spectra_ex or
+// ffst_batch_create call (nested calls count towards the outer one) returns
+// hipErrorOutOfMemory without allocating, so every cleanup path can be run.
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_live;
+std::atomic<size_t> g_live_bytes{0};
+thread_local int t_alloc_depth = 0;
+thread_local int t_alloc_calls = 0;
+
+int fault_alloc_index() {
+  const char* v = std::getenv("FFST_FAULT_ALLOC");
+  return v ? std::atoi(v) : 0;
+}
+}  // namespace
+
+ffst::AllocScope::AllocScope() {
+  if (t_alloc_depth++ == 0) t_alloc_calls = 0;
+}
+ffst::AllocScope::~AllocScope() { --t_alloc_depth; }
+
+hipError_t ffst::dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  const int fail_at = fault_alloc_index();
+  if (fail_at > 0 && ++t_alloc_calls == fail_at) return hipErrorOutOfMemory;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_live[*p] = bytes;
+  g_live_bytes += bytes;
+  return hipSuccess;
+}
+
+void ffst::dev_free(void* p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_live.find(p);
+    if (it != g_live.end()) {
+      g_live_bytes -= it->second;
+      g_live.erase(it);
+    }
+  }
+  (void)hipFree(p);
 }
 
 namespace {
@@ -170,9 +226,7 @@ std::vector<float2> twiddles(int L) {
 }
 
 // Frees device memory whose release status no caller can act on.
-void release(void* ptr) {
-  if (ptr) (void)hipFree(ptr);
-}
+void release(void* ptr) { dev_free(ptr); }
 
 void release_event(hipEvent_t e) {
   if (e) (void)hipEventDestroy(e);
@@ -182,7 +236,7 @@ template <class T>
 hipError_t upload(T** dst, const std::vector<T>& src) {
   *dst = nullptr;
   if (src.empty()) return hipSuccess;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  hipError_t e = dev_alloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
 }
@@ -310,7 +364,7 @@ void cyclic_window(const unsigned char* f, int N, int* lo, int* w) {
 hipError_t one_sided_spectra(ffst_plan* p, const GenParams& g, const int* d_kind, const int* d_j, const int* d_k) {
   const int M = p->M, N = p->N, eta = p->eta;
   unsigned char* d_flags = nullptr;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_flags), (size_t)eta * N);
+  hipError_t e = dev_alloc(reinterpret_cast<void**>(&d_flags), (size_t)eta * N);
   if (e != hipSuccess) return e;
   e = timed(KID_ONE_SIDED, nullptr,
             [&] { return launch_one_sided_flags(p->psi, M, N, eta, d_kind, d_j, d_k, d_flags, nullptr); });
@@ -331,7 +385,7 @@ hipError_t one_sided_spectra(ffst_plan* p, const GenParams& g, const int* d_kind
   if ((e = upload(&p->d_lo, p->lo)) != hipSuccess || (e = upload(&p->d_w, p->w)) != hipSuccess ||
       (e = upload(&p->d_poff, p->poff)) != hipSuccess)
     return e;
-  if ((e = hipMalloc(reinterpret_cast<void**>(&p->psip), (size_t)std::max(total, 1LL) * sizeof(float))) != hipSuccess)
+  if ((e = dev_alloc(reinterpret_cast<void**>(&p->psip), (size_t)std::max(total, 1LL) * sizeof(float))) != hipSuccess)
     return e;
   e = timed(KID_ONE_SIDED, nullptr, [&] {
     return launch_one_sided_pack(g, eta, max_w, d_kind, d_j, d_k, p->d_lo, p->d_w, p->d_poff, p->psip, nullptr);
@@ -381,6 +435,7 @@ extern "C" {
 int ffst_spectra(int M, int N, int J, ffst_plan** out) { return ffst_spectra_ex(M, N, J, nullptr, out); }
 
 int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** out) {
+  const AllocScope alloc_scope;
   if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
   *out = nullptr;
   if (M < 4 || N < 4) return fail(FFST_EINVAL, "image sides must be >= 4 (got %d x %d)", M, N);
@@ -428,7 +483,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   int *d_kind = nullptr, *d_j = nullptr, *d_k = nullptr;
   int *d_lo = nullptr, *d_hi = nullptr;
   const size_t psi_elems = (size_t)p->eta * M * p->H;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->psi), psi_elems * sizeof(float));
+  hipError_t e = dev_alloc(reinterpret_cast<void**>(&p->psi), psi_elems * sizeof(float));
   if (e != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "spectra allocation (%zu bytes): %s", psi_elems * 4, hipGetErrorString(e));
@@ -468,7 +523,8 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   release(d_kind); release(d_j); release(d_k); release(d_lo); release(d_hi);
   if (e != hipSuccess) {
     free_plan(p);
-    return fail(FFST_EDEVICE, "spectra generation: %s", hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? FFST_ENOMEM : FFST_EDEVICE, "spectra generation: %s",
+                hipGetErrorString(e));
   }
 
   // Compact per-plane windows and the work lists of the column kernels.
@@ -599,8 +655,8 @@ int ffst_plan_windows(const ffst_plan* p, int* first_col, int* last_col) {
   return ok();
 }
 
-static_assert(FFST_KIND_LOWPASS == KIND_LOWPASS && FFST_KIND_HORIZONTAL == KIND_H && FFST_KIND_VERTICAL == KIND_V &&
-                  FFST_KIND_SEAM == KIND_SEAM,
+static_assert((int)FFST_KIND_LOWPASS == (int)KIND_LOWPASS && (int)FFST_KIND_HORIZONTAL == (int)KIND_H &&
+                  (int)FFST_KIND_VERTICAL == (int)KIND_V && (int)FFST_KIND_SEAM == (int)KIND_SEAM,
               "public and internal spectrum kinds must agree");
 
 int ffst_scale_shear(int J, int i, int* kind, int* j, int* k) {
@@ -914,6 +970,13 @@ void ffst_destroy(ffst_plan* p) {
 }
 
 const char* ffst_last_error(void) { return g_err.c_str(); }
+
+#ifndef FFST_BUILD_ID
+#define FFST_BUILD_ID "unknown"
+#endif
+const char* ffst_build_id(void) { return FFST_BUILD_ID; }
+
+size_t ffst_device_bytes(void) { return g_live_bytes.load(); }
 
 int ffst_profile_enable(unsigned mask) {
   g_mask.store(mask, std::memory_order_relaxed);

@@ -5,8 +5,9 @@
 // plan's batched passes on a stream of its own, forked from a capture stream
 // by an event and joined back by one event per class. The whole fork/join is
 // captured into a HIP graph, instantiated once per (input, output, workspace)
-// triple and launched on the caller's stream; the classes' kernels can then
-// run side by side on the GPU with no host work between them.
+// triple (the eight most recently used triples per direction are kept) and
+// launched on the caller's stream; the classes' kernels can then run side by
+// side on the GPU with no host work between them.
 #include "../../include/ffst.h"
 #include "internal.hpp"
 #include "launch_cfg.hpp"
@@ -21,6 +22,10 @@ using namespace ffst;
 namespace {
 
 constexpr unsigned kBatchMagic = 0x46464254u;  // "FFBT"
+// Executable graphs kept per direction: callers that let the binding
+// allocate a fresh output per call (or alternate between a few buffers)
+// replay graphs instead of capturing one per call.
+constexpr size_t kGraphsPerDirection = 8;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -47,7 +52,12 @@ struct ffst_batch {
     const void* in = nullptr;
     const void* out = nullptr;
     const void* ws = nullptr;
-  } graphs[2];                              // 0: forward, 1: adjoint
+    unsigned long long last_use = 0;
+  };
+  // per direction (0: forward, 1: adjoint), the executable graphs of the
+  // most recently used (input, output, workspace) triples
+  std::vector<Graph> graphs[2];
+  unsigned long long uses = 0;
   unsigned magic = 0;
 };
 
@@ -56,9 +66,10 @@ namespace {
 bool batch_ok(const ffst_batch* b) { return b && b->magic == kBatchMagic; }
 
 void drop_graphs(ffst_batch* b) {
-  for (auto& g : b->graphs) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    g = ffst_batch::Graph{};
+  for (auto& dir : b->graphs) {
+    for (auto& g : dir)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    dir.clear();
   }
 }
 
@@ -149,16 +160,29 @@ int run(ffst_batch* b, int dir, const float* in, float* out, void* ws, void* str
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
     return fail(FFST_EINVAL, "%s: the current device is not the batch's device %d", what, b->device);
-  ffst_batch::Graph& g = b->graphs[dir];
-  if (!g.exec || g.in != in || g.out != out || g.ws != ws) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    g = ffst_batch::Graph{};
+  std::vector<ffst_batch::Graph>& cache = b->graphs[dir];
+  ffst_batch::Graph* g = nullptr;
+  for (auto& c : cache)
+    if (c.in == in && c.out == out && c.ws == ws) g = &c;
+  if (!g) {
     hipGraphExec_t exec = nullptr;
     const int st = capture(b, dir, in, out, ws, &exec);
     if (st != FFST_OK) return st;
-    g = ffst_batch::Graph{exec, in, out, ws};
+    if (cache.size() >= kGraphsPerDirection) {  // replace the least recently used
+      auto lru = std::min_element(cache.begin(), cache.end(), [](const ffst_batch::Graph& x,
+                                                                 const ffst_batch::Graph& y) {
+        return x.last_use < y.last_use;
+      });
+      (void)hipGraphExecDestroy(lru->exec);
+      *lru = ffst_batch::Graph{exec, in, out, ws, 0};
+      g = &*lru;
+    } else {
+      cache.push_back(ffst_batch::Graph{exec, in, out, ws, 0});
+      g = &cache.back();
+    }
   }
-  const hipError_t e = hipGraphLaunch(g.exec, static_cast<hipStream_t>(stream));
+  g->last_use = ++b->uses;
+  const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(FFST_EDEVICE, "%s: hipGraphLaunch: %s", what, hipGetErrorString(e));
   return FFST_OK;
 }
@@ -196,6 +220,7 @@ extern "C" {
 
 int ffst_batch_create(int count, const int* M, const int* N, const int* J, const ffst_options* opt,
                       ffst_batch** out) {
+  const AllocScope alloc_scope;
   if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
   *out = nullptr;
   if (count < 1) return fail(FFST_EINVAL, "count must be >= 1 (got %d)", count);

@@ -169,6 +169,16 @@ struct CAdjLineArgs {
 };
 hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s);
 
+// Device memory of plans and batches (counted for ffst_device_bytes; the
+// FFST_FAULT_ALLOC test hook fails the n-th allocation inside one creation
+// call, counted from the outermost AllocScope).
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+struct AllocScope {
+  AllocScope();
+  ~AllocScope();
+};
+
 // Error reporting shared by the C ABI files: stores the message returned by
 // ffst_last_error on this thread and returns `status`.
 int fail(int status, const char* fmt, ...);

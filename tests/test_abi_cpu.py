@@ -113,3 +113,14 @@ def test_python_wrappers_raise(lib):
     with pytest.raises(_lib.FfstError) as e:
         _lib.ffst_spectra(320, 512, 3)
     assert e.value.status == _lib.FFST_EUNSUPPORTED
+
+
+def test_build_id_ties_the_library_to_its_sources(lib):
+    # the library in the tree was built from the sources in the tree ...
+    from paper_1202_1773_amd.build import build_id
+    assert _lib.ffst_build_id() == build_id()
+    assert len(build_id()) == 16
+    # ... and a library built from other sources is refused at load time
+    with pytest.raises(ImportError, match="built from other sources"):
+        _lib.check_build_id("0123456789abcdef", build_id())
+    _lib.check_build_id(build_id(), build_id())

@@ -204,3 +204,28 @@ def test_batch_argument_checks():
     with pytest.raises(ValueError):
         bp.forward(f[:-1])
     bp.close()
+
+
+def test_graphs_of_several_output_buffers_are_kept():
+    # Alternating between output buffers (and fresh outputs from the binding)
+    # replays the graphs kept for each (input, output, workspace) triple; every
+    # result equals the first.
+    log("uneven batch: graphs of several output buffers")
+    imgs = small_images()
+    bp = BatchPlan(SMALL, SMALL_J)
+    f = bp.pack([torch.from_numpy(i) for i in imgs])
+    outs = [bp.empty_coefficients() for _ in range(3)]
+    first = bp.forward(f, out=outs[0]).clone()
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            assert torch.equal(bp.forward(f, out=o), first), rep
+    fresh = [bp.forward(f) for _ in range(10)]   # more triples than the cache holds
+    torch.cuda.synchronize()
+    for c in fresh:
+        assert torch.equal(c, first)
+    ys = [bp.adjoint(first) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[1], ys[2])
+    bp.close()

@@ -1,7 +1,9 @@
 """Every FFT length the library is compiled for, once as the column length M
 and once as the row length N (odd N through the odd-row kernels), with real
 and complex shearlets, against the FP64 oracle: each kernel instantiation
-runs at least once with its own data."""
+runs at least once with its own data. Planes whose oracle norm is
+negligible (<= 1e-12 ||f||, spectra that vanish on small grids) are not
+compared relatively; the GPU must write (numerically) zero there instead."""
 
 import numpy as np
 import pytest
@@ -42,11 +44,15 @@ def _check(M, N, J, complex_shearlets, batch=1):
             den = np.sqrt((np.abs(ref) ** 2).sum(axis=(-2, -1)))
             big = den > 1e-12 * np.linalg.norm(f)
             err = max(err, float((num[big] / den[big]).max()))
+            # planes the oracle gives as (numerically) zero must be ~0 on the GPU
+            assert np.abs(got[~big]).max(initial=0.0) <= 1e-11 * np.linalg.norm(f), (M, N, b)
         else:
             ref = oracle_forward(f, M, N, J)
             den = np.sqrt((ref ** 2).sum(axis=(-2, -1)))
             big = den > 1e-12 * np.linalg.norm(f)
-            err = max(err, float(per_plane_rel_l2(c[b].cpu().numpy()[big], ref[big]).max()))
+            got = c[b].cpu().numpy()
+            err = max(err, float(per_plane_rel_l2(got[big], ref[big]).max()))
+            assert np.abs(got[~big]).max(initial=0.0) <= 1e-11 * np.linalg.norm(f), (M, N, b)
         rec = max(rec, rel_l2(y[b], f))
     plan.close()
     return err, rec
