@@ -173,6 +173,23 @@ int ffst_forward(const ffst_plan* plan, const float* f, float* coeffs, int batch
                  void* ws, void* stream);
 
 /*
+ * Forward transform for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and kernels as ffst_forward, with the
+ * workspace taken from a static device array of the library (64 MiB =
+ * 67108864 bytes per GPU, held by every GPU the library runs on until the
+ * process ends) instead of a caller buffer. The call allocates
+ * nothing and creates no HIP objects (kernel timing is skipped). Batches whose
+ * workspace (ffst_workspace_size) exceeds the limit are rejected with
+ * FFST_EINVAL before anything runs. The scratch needs no initial contents
+ * (every byte the kernels read is written first in the same call). All calls
+ * on one GPU share that GPU's array: calls that may overlap in time on one
+ * GPU (other streams, other host threads) race and must be serialised by the
+ * caller. Real-shearlet plans only; layouts and errors as ffst_forward.
+ */
+int ffst_forward_noalloc(const ffst_plan* plan, const float* f, float* coeffs, int batch, void* stream);
+
+/*
  * Adjoint: f[b] = ifft2( sum_i Psi_i .* fft2(coeffs[b][i]) ). Overwrites f
  * (does not accumulate). Asynchronous on `stream`.
  */

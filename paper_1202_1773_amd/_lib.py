@@ -30,7 +30,8 @@ KIND_NAMES = {FFST_KIND_LOWPASS: "lowpass", FFST_KIND_HORIZONTAL: "horizontal", 
 
 EXPORTED = [
     "ffst_spectra", "ffst_spectra_ex", "ffst_plan_info", "ffst_workspace_size",
-    "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_adjoint",
+    "ffst_get_spectra", "ffst_plan_windows", "ffst_forward", "ffst_forward_noalloc",
+    "ffst_adjoint",
     "ffst_inverse", "ffst_adjoint_sign", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
     "ffst_scale_shear", "ffst_shearlet_index",
     "ffst_set_tuning", "ffst_get_tuning", "ffst_tune",
@@ -88,6 +89,7 @@ def load():
         "ffst_get_spectra": (I, [P, P, I]),
         "ffst_plan_windows": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "ffst_forward": (I, [P, P, P, I, P, P]),
+        "ffst_forward_noalloc": (I, [P, P, P, I, P]),
         "ffst_adjoint": (I, [P, P, P, I, P, P]),
         "ffst_inverse": (I, [P, P, P, I, P, P]),
         "ffst_adjoint_sign": (I, [P, P, P, I, P, P, P]),
@@ -196,6 +198,12 @@ def ffst_plan_windows(plan, eta):
 def ffst_forward(plan, f_ptr, c_ptr, batch, ws_ptr, stream_ptr):
     _check(load().ffst_forward(plan, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), int(batch),
                                ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream_ptr)), "ffst_forward")
+
+
+def ffst_forward_noalloc(plan, f_ptr, c_ptr, batch, stream_ptr):
+    _check(load().ffst_forward_noalloc(plan, ctypes.c_void_p(f_ptr), ctypes.c_void_p(c_ptr), int(batch),
+                                       ctypes.c_void_p(stream_ptr)), "ffst_forward_noalloc")
+
 
 
 def ffst_adjoint(plan, c_ptr, f_ptr, batch, ws_ptr, stream_ptr):

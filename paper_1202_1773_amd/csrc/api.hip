@@ -160,9 +160,13 @@ hipEvent_t pooled_event() {
   return e;
 }
 
+// Set for the duration of a call that must not create HIP objects (events).
+thread_local bool t_no_timing = false;
+
 template <class Fn>
 hipError_t timed(int id, hipStream_t s, Fn&& fn) {
-  if (g_profile_suspended.load(std::memory_order_relaxed) || !((g_mask.load(std::memory_order_relaxed) >> id) & 1u))
+  if (t_no_timing || g_profile_suspended.load(std::memory_order_relaxed) ||
+      !((g_mask.load(std::memory_order_relaxed) >> id) & 1u))
     return fn();
   ProfRec r{id, pooled_event(), pooled_event()};
   if (!r.a || !r.b) return fn();
@@ -416,6 +420,43 @@ Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_
 }  // namespace
 
 void ffst::profile_suspend(bool on) { g_profile_suspended.store(on, std::memory_order_relaxed); }
+
+// ---- static scratch for callers that cannot allocate -------------------
+//
+// ffst_forward_noalloc runs ffst_forward with its workspace in this
+// file-scope device array instead of caller memory. Every GPU the library
+// runs on holds its own copy for the life of the process. In host code the
+// name `scratch` is only a host-side stand-in: its device address on the
+// current device comes from hipGetSymbolAddress, looked up once per device
+// (with that device current) and kept in g_scratch_ptr; only that pointer
+// is handed to kernels.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FFST_EUNSUPPORTED, "device %d beyond the static scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FFST_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FFST_OK;
+}
+
+struct NoTimingScope {
+  bool saved;
+  NoTimingScope() : saved(t_no_timing) { t_no_timing = true; }
+  ~NoTimingScope() { t_no_timing = saved; }
+};
+}  // namespace
 
 size_t ffst::workspace_upper_bound(const ffst_plan* p, int batch) {
   if (!plan_ok(p) || batch <= 0) return 0;
@@ -726,6 +767,27 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
     }
   }
   return launched(e, "ffst_forward");
+}
+
+int ffst_forward_noalloc(const ffst_plan* p, const float* f, float* coeffs, int batch, void* stream) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (reject_kind(p, false, "ffst_forward_noalloc") != FFST_OK) return FFST_EINVAL;
+  if (batch < 0) return fail(FFST_EINVAL, "batch must be >= 0 (got %d)", batch);
+  if (batch == 0) return FFST_OK;
+  const size_t need = ws_bytes(p, batch);
+  if (need > kStaticScratchBytes)
+    return fail(FFST_EINVAL,
+                "ffst_forward_noalloc: %d image(s) of %d x %d, J = %d need %zu bytes of scratch; the static scratch "
+                "holds %zu (use ffst_forward with a workspace, or fewer images per call)",
+                batch, p->M, p->N, p->J, need, kStaticScratchBytes);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FFST_EDEVICE, "hipGetDevice failed");
+  if (dev != p->device) return fail(FFST_EINVAL, "current device %d is not the plan's device %d", dev, p->device);
+  void* ws = nullptr;
+  const int st = static_scratch(dev, &ws);
+  if (st != FFST_OK) return st;
+  const NoTimingScope no_events;   // kernel timing would create HIP events
+  return ffst_forward(p, f, coeffs, batch, ws, stream);
 }
 
 namespace {

@@ -73,6 +73,7 @@ def test_calls_reject_bad_plans(lib):
     assert lib.ffst_plan_info(None, ctypes.byref(z), None, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_workspace_size(None, 1) == 0
     assert lib.ffst_forward(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
+    assert lib.ffst_forward_noalloc(None, None, None, 1, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_adjoint(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_inverse(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
     assert lib.ffst_forward_complex(None, None, None, 1, None, None) == _lib.FFST_EBADPLAN
