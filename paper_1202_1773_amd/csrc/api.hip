@@ -34,6 +34,11 @@ struct ffst_plan {
   int* d_img_w = nullptr;
   long long* d_img_off = nullptr;
   int2* d_lines = nullptr;      // forward column lines (spectrum, column), by spectrum
+  // real shearlets: every window column line of Psi_i over its cyclic nonzero
+  // hull (see FwdLineArgs), for the forward lines and the adjoint's CSR entries
+  float* psic = nullptr;
+  int4* d_line_hull = nullptr;
+  int4* d_col_hull = nullptr;
   int* d_col_ptr = nullptr;     // per plane group: columns -> spectra (CSR, absolute pointers)
   int* d_col_planes = nullptr;
   // complex shearlets: compact one-sided spectra over cyclic full-plane windows
@@ -248,7 +253,8 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
-                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent};
+                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent,
+                  p->psic, p->d_line_hull, p->d_col_hull};
   for (void* b : bufs)
     if (b) release(b);
   p->magic = 0;
@@ -413,6 +419,64 @@ struct TuningScope {
   explicit TuningScope(const ffst_plan* p) : saved(t_blocks_per_cu) { t_blocks_per_cu = p->tune_blocks_per_cu; }
   ~TuningScope() { t_blocks_per_cu = saved; }
 };
+
+// Smallest cyclic range [lo, lo + K) (mod M) holding every nonzero value of
+// a column line: the complement of its longest cyclic run of zeros (the
+// first such run on ties). K = 0 for an all-zero line.
+void cyclic_hull(const float* col, int M, int* lo, int* K) {
+  int first_nz = -1;
+  for (int r = 0; r < M && first_nz < 0; ++r)
+    if (col[r] != 0.f) first_nz = r;
+  if (first_nz < 0) {
+    *lo = 0;
+    *K = 0;
+    return;
+  }
+  // scan the rotation that starts at a nonzero value, so every zero run is
+  // contiguous in the scan
+  int best = 0, best_end = first_nz, run = 0;
+  for (int m = 1; m <= M; ++m) {
+    const int r = (first_nz + m) % M;
+    if (m < M && col[r] == 0.f) {
+      ++run;
+    } else {
+      if (run > best) {
+        best = run;
+        best_end = r;                 // first nonzero after the run
+      }
+      run = 0;
+    }
+  }
+  *lo = best > 0 ? best_end : first_nz;
+  *K = M - best;
+}
+
+// Psi_i over the hulls of its window column lines: values appended to psic,
+// one (r_lo, K, offset) per line in plane order (hull_of[base[i] + c - lo_i]).
+hipError_t spectrum_hulls(const ffst_plan* p, std::vector<float>& psic, std::vector<int4>& hull_of,
+                          std::vector<long long>& base) {
+  const int M = p->M;
+  base.assign(p->eta + 1, 0);
+  std::vector<float> buf;
+  for (int i = 0; i < p->eta; ++i) {
+    base[i + 1] = base[i] + p->w[i];
+    if (p->w[i] == 0) continue;
+    buf.resize((size_t)p->w[i] * M);
+    const hipError_t e = hipMemcpy(buf.data(), p->psi + ((size_t)i * p->H + p->lo[i]) * M, buf.size() * sizeof(float),
+                                   hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int m = 0; m < p->w[i]; ++m) {
+      const float* col = buf.data() + (size_t)m * M;
+      int lo = 0, K = 0;
+      cyclic_hull(col, M, &lo, &K);
+      if (psic.size() + (size_t)K > (size_t)INT32_MAX) return hipErrorInvalidValue;
+      hull_of.push_back(make_int4(lo, K, (int)psic.size(), 0));
+      for (int k = 0; k < K; ++k) psic.push_back(col[(lo + k) % M]);
+    }
+  }
+  if (psic.empty()) psic.push_back(0.f);
+  return hipSuccess;
+}
 
 Windows plane_windows(const ffst_plan* p) { return Windows{p->d_lo, p->d_w, p->d_off}; }
 Windows image_window(const ffst_plan* p) { return Windows{p->d_img_lo, p->d_img_w, p->d_img_off}; }
@@ -640,13 +704,31 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       col_ptr.push_back(cplx ? (int)col_ent.size() : (int)col_planes.size());
     }
   }
+  std::vector<float> psic;
+  std::vector<int4> line_hull, col_hull;
+  if (!cplx) {
+    std::vector<int4> hull_of;
+    std::vector<long long> hbase;
+    if ((e = spectrum_hulls(p, psic, hull_of, hbase)) != hipSuccess) {
+      free_plan(p);
+      return fail(e == hipErrorOutOfMemory ? FFST_ENOMEM : FFST_EDEVICE, "spectrum hulls: %s", hipGetErrorString(e));
+    }
+    auto hull = [&](int i, int c) { return hull_of[hbase[i] + (c - p->lo[i])]; };
+    for (const int2& l : lines) line_hull.push_back(hull(l.x, l.y));
+    for (int g = 0; g < ngroups; ++g)
+      for (int c = 0; c < p->H; ++c)
+        for (int t = col_ptr[g * (p->H + 1) + c]; t < col_ptr[g * (p->H + 1) + c + 1]; ++t)
+          col_hull.push_back(hull(col_planes[t], c));
+  }
   std::vector<int> img_lo{0}, img_w{p->H};
   std::vector<long long> img_off{0};
   if ((!p->d_lo && (e = upload(&p->d_lo, p->lo)) != hipSuccess) ||
       (!p->d_w && (e = upload(&p->d_w, p->w)) != hipSuccess) || (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
       (e = upload(&p->d_lines, lines)) != hipSuccess || (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
-      (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess) {
+      (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess ||
+      (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_line_hull, line_hull)) != hipSuccess ||
+      (e = upload(&p->d_col_hull, col_hull)) != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
@@ -756,7 +838,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
       const int p0 = p->groups[g], p1 = p->groups[g + 1];
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
-      FwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psi, p->d_lines + p->line_ptr[p0],
+      FwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_line_hull + p->line_ptr[p0], p->d_lines + p->line_ptr[p0],
                      p->line_ptr[p1] - p->line_ptr[p0], nimg, p->pitch, plane_windows(p), unit_stride, base, Y,
                      scale, p->twM};
       e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_lines(fa, s); });
@@ -823,8 +905,8 @@ int adjoint_real(const ffst_plan* p, const float* coeffs, float* f, int batch, v
                  p1 - p0, p0, p->M, p->N, p->pitch, plane_windows(p), p->twN, sign_scale};
       e = timed(KID_R2C_PLANES, s, [&] { return launch_r2c_rows(rr, s); });
       if (e != hipSuccess) break;
-      AdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psi,
-                     p->d_col_ptr + g * (p->H + 1), p->d_col_planes, nimg, sc.nparts, g > 0 ? 1 : 0,
+      AdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psic,
+                     p->d_col_ptr + g * (p->H + 1), p->d_col_planes, p->d_col_hull, nimg, sc.nparts, g > 0 ? 1 : 0,
                      sc.fused ? 1 : 0, p->pitch, sc.fused ? A + img0 * MH : P, scale, p->twM};
       e = timed(KID_ADJ_COLS, s, [&] { return launch_adj_lines(aa, s); });
     }

@@ -82,10 +82,14 @@ hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s);
 hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse, const float2* parts, int nparts,
                            long long part_stride, const float2* twM, hipStream_t s);
 
+// Spectrum column lines over their cyclic nonzero hull: line (i, c) holds
+// Psi_i at rows (r_lo + m) mod M, m < K, at psic + off; elsewhere Psi_i is
+// zero on that column. A line's hull is the int4 (r_lo, K, off, 0).
 struct FwdLineArgs {
   int M, N;
   const float2* F;          // [nimg][N/2+1][M]
-  const float* psi;         // [eta][N/2+1][M]
+  const float* psic;        // compact spectrum lines
+  const int4* hull;         // per line: (r_lo, K, off, 0)
   const int2* lines;        // (spectrum, column)
   int nlines, nimg;
   int pitch;                // complex elements between column lines of F and Y
@@ -102,9 +106,10 @@ struct AdjLineArgs {
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psi;
+  const float* psic;        // compact spectrum lines
   const int* col_ptr;
   const int* col_planes;
+  const int4* col_hull;     // hull of (col_planes[t], column) for every CSR entry t
   int nimg, nparts, accumulate, fused;
   int pitch;                // complex elements between column lines of Z, A and partial sums
   float2* out;

@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __rest
 
 struct FwdLineJob {
   const float2* F;          // [nimg][H][M]
-  const float* psi;         // [eta][H][M]
+  const float* psic;        // compact spectrum lines (see FwdLineArgs)
+  const int4* hull;         // per line: (r_lo, K, off, 0)
   const int2* lines;        // (spectrum, column) of the unit's lines
   int nlines, nimg, H;
   int pitch;                // complex elements between column lines of F and Y
@@ -78,7 +79,16 @@ struct FwdLineJob {
   const float2* twM;
 };
 
-// Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image).
+// Index m of element e of a column line inside the line's cyclic hull
+// [r_lo, r_lo + K) (mod L), or a value >= K when e lies outside it.
+template <int L>
+__device__ __forceinline__ int hull_index(int e, int r_lo) {
+  const int d = e - r_lo;
+  return d < 0 ? d + L : d;
+}
+
+// Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image);
+// Psi_i[c] and F[c] are read only inside the line's hull (zero elsewhere).
 template <int M>
 __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob job) {
   using C = LineCfg<M>;
@@ -100,13 +110,18 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob jo
     const int q = u * C::LPB + g;
     const int qq = q < total ? q : 0;
     const int img = qq / job.nlines;
-    const int2 ln = job.lines[qq % job.nlines];
+    const int li = qq % job.nlines;
+    const int2 ln = job.lines[li];
+    const int4 hl = job.hull[li];
     const float2* fb = job.F + ((long long)img * job.H + ln.y) * job.pitch;
-    const float* pb = job.psi + ((long long)ln.x * job.H + ln.y) * M;
+    const float* pb = job.psic + hl.z;
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      fn[s] = fb[j + G * s];
-      pn[s] = pb[j + G * s];
+      const int e = j + G * s;
+      const int m = hull_index<M>(e, hl.x);
+      const bool in = m < hl.y;
+      fn[s] = in ? fb[e] : make_float2(0.f, 0.f);
+      pn[s] = in ? pb[m] : 0.f;
     }
   };
   int u = blockIdx.x;
@@ -136,9 +151,10 @@ struct AdjLineJob {
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psi;
+  const float* psic;        // compact spectrum lines (see FwdLineArgs)
   const int* col_ptr;       // CSR over columns -> spectra of this plane group
   const int* col_planes;
+  const int4* col_hull;     // hull of every CSR entry's line
   int H, nimg, nparts;
   int pitch;                // complex elements between column lines of Z, A and the partial sums
   int accumulate;           // add to the existing partial sums
@@ -181,12 +197,14 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
     float pn[V];
     if (t < q1) {
       const int i = job.col_planes[t];
+      const int4 hl = job.col_hull[t];
       const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
-      const float* pb = job.psi + ((long long)i * job.H + c) * M;
+      const float* pb = job.psic + hl.z;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         zn[s] = zb[j + G * s];
-        pn[s] = pb[j + G * s];
+        const int m = hull_index<M>(j + G * s, hl.x);
+        pn[s] = m < hl.y ? pb[m] : 0.f;
       }
     }
     for (; t < q1; t += job.nparts) {
@@ -200,12 +218,14 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
       const int tn = t + job.nparts;
       if (tn < q1) {
         const int i = job.col_planes[tn];
+        const int4 hl = job.col_hull[tn];
         const float2* zb = zimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
-        const float* pb = job.psi + ((long long)i * job.H + c) * M;
+        const float* pb = job.psic + hl.z;
 #pragma unroll
         for (int s = 0; s < V; ++s) {
           zn[s] = zb[j + G * s];
-          pn[s] = pb[j + G * s];
+          const int m = hull_index<M>(j + G * s, hl.x);
+          pn[s] = m < hl.y ? pb[m] : 0.f;
         }
       }
       fft_group<M, V, false, C::SYNC>(v, j, my, tw);
@@ -236,17 +256,11 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
   }
 }
 
-// For powers of two 64 <= M <= 512 the body fits 128 registers (4 waves per
-// SIMD) with a few spills; other lengths (16-value lanes from 1024 on, the
-// 12-value lanes of 3 * 2^k) keep the compiler's own allocation.
+// The compiler's own register allocation (no occupancy target): capping
+// the 512-point body at 128 registers (4 waves per SIMD) spilled to scratch
+// and was slower than 3 waves without spills.
 template <int M, bool FUSED>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
-k_adj_lines(AdjLineJob job) {
-  adj_lines_body<M, FUSED>(job);
-}
-
-template <int M, bool FUSED>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines_wide(AdjLineJob job) {
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob job) {
   adj_lines_body<M, FUSED>(job);
 }
 
@@ -294,7 +308,7 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
 }
 
 hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
-  FwdLineJob job{a.F, a.psi, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.pitch, a.win, a.y_img_stride,
+  FwdLineJob job{a.F, a.psic, a.hull, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.pitch, a.win, a.y_img_stride,
                  a.y_off_base, a.Y, a.scale, a.twM};
   if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
   const long long total = (long long)job.nlines * job.nimg;
@@ -313,8 +327,8 @@ hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
-  AdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psi, a.col_ptr, a.col_planes, a.N / 2 + 1,
-                 a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
+  AdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psic, a.col_ptr, a.col_planes, a.col_hull,
+                 a.N / 2 + 1, a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
   if (job.nimg == 0) return hipSuccess;
   const long long total = (long long)job.H * job.nimg * job.nparts;
   switch (a.M) {
@@ -322,17 +336,10 @@ hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
   case n: {                                                                                       \
     const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
     const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if constexpr (n >= 64 && n <= 512 && n % 3 != 0) {                                             \
-      if (a.fused)                                                                                \
-        hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                       \
-      else                                                                                        \
-        hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                      \
-    } else {                                                                                      \
-      if (a.fused)                                                                                \
-        hipLaunchKernelGGL((k_adj_lines_wide<n, true>), grid, block, 0, s, job);                  \
-      else                                                                                        \
-        hipLaunchKernelGGL((k_adj_lines_wide<n, false>), grid, block, 0, s, job);                 \
-    }                                                                                             \
+    if (a.fused)                                                                                  \
+      hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                         \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                        \
     return hipGetLastError();                                                                     \
   }
     FFST_COL_CASES(CASE)
