@@ -303,7 +303,7 @@ def bench_large(steps, warmup, tune):
     rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
     out = {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
            "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
-           "reconstruction_rel_l2": rec, "launch_tuning": plan.tuning()}
+           "reconstruction_rel_l2": rec, "launch_tuning": plan.tuning_ex()}
     plan.close()
     return out
 
@@ -355,7 +355,7 @@ def main():
         # launch settings picked by the autotuner, per plan, before any timing
         plan.tune(x)
         plan1.tune(x[0])
-        tuning = {"batched": plan.tuning(), "plain": plan1.tuning()}
+        tuning = {"batched": plan.tuning_ex(), "plain": plan1.tuning_ex()}
     plan.workspace(B)
     plan1.workspace(1)
 

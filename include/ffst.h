@@ -248,8 +248,36 @@ int ffst_set_tuning(ffst_plan* plan, int nparts, int blocks_per_cu);
 int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
 
 /*
+ * All launch settings of a plan, including the kernel shapes compiled in
+ * more than one form (real-shearlet passes; the complex shearlets' own column
+ * kernels always take the defaults):
+ *   col_values  values per lane of the column-direction FFTs: 0 = the default
+ *               for the column length M (8 below 1024, 16 from 1024 on for
+ *               powers of two; 12 for 3 * 2^k), or the alternative compiled for
+ *               M (16 / 8 for powers of two from 64 on, 6 for 3 * 2^k from 96
+ *               on); ffst_get_tuning_ex reports the value in use
+ *   row_block   rows per block of the row-direction FFTs: 0 or 1 = the default
+ *               height, 2 = the alternative one, twice the default for rows of
+ *               up to 512 points (4 .. 16 lanes per row) and half of it for
+ *               longer rows (row lengths 64 .. 4096 that are powers of two or
+ *               3 * 2^k)
+ * Other values are rejected with FFST_EINVAL. Every setting computes the same
+ * transform; only the rounding order of the FFT stages and of the adjoint's
+ * sums differs.
+ */
+typedef struct {
+    int nparts;
+    int blocks_per_cu;
+    int col_values;
+    int row_block;
+} ffst_tuning;
+int ffst_set_tuning_ex(ffst_plan* plan, const ffst_tuning* tuning);
+int ffst_get_tuning_ex(const ffst_plan* plan, ffst_tuning* tuning);
+
+/*
  * Autotuner: times forward + adjoint of `batch` images (f, read) for every
- * setting nparts in {1, 2, 4, 8} x blocks_per_cu in {0, 1, 2, 4, 8, 16} whose
+ * setting nparts in {1, 2, 4, 8} x blocks_per_cu in {0, 1, 2, 4, 8, 16} x the
+ * compiled col_values x row_block forms (ffst_tuning) whose
  * workspace fits in ws_size bytes (the best of 3 runs after one warm-up, HIP
  * events on `stream`), and keeps the fastest in the plan. coeffs (the
  * coefficient buffer for the plan's kind, as for the transform calls) and

@@ -34,7 +34,7 @@ EXPORTED = [
     "ffst_adjoint",
     "ffst_inverse", "ffst_adjoint_sign", "ffst_forward_complex", "ffst_adjoint_complex", "ffst_inverse_complex",
     "ffst_scale_shear", "ffst_shearlet_index",
-    "ffst_set_tuning", "ffst_get_tuning", "ffst_tune",
+    "ffst_set_tuning", "ffst_get_tuning", "ffst_set_tuning_ex", "ffst_get_tuning_ex", "ffst_tune",
     "ffst_batch_create", "ffst_batch_info", "ffst_batch_class", "ffst_batch_layout",
     "ffst_batch_workspace_size", "ffst_batch_forward", "ffst_batch_adjoint", "ffst_batch_inverse",
     "ffst_batch_tune", "ffst_batch_destroy",
@@ -47,6 +47,11 @@ class FfstError(RuntimeError):
     def __init__(self, status, where, message):
         super().__init__(f"{where} failed with status {status}: {message}")
         self.status = status
+
+
+class ffst_tuning(ctypes.Structure):
+    _fields_ = [("nparts", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("col_values", ctypes.c_int),
+                ("row_block", ctypes.c_int)]
 
 
 class ffst_options(ctypes.Structure):
@@ -100,6 +105,8 @@ def load():
         "ffst_shearlet_index": (I, [I, I, I, I, ctypes.POINTER(I)]),
         "ffst_set_tuning": (I, [P, I, I]),
         "ffst_get_tuning": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ffst_set_tuning_ex": (I, [P, ctypes.POINTER(ffst_tuning)]),
+        "ffst_get_tuning_ex": (I, [P, ctypes.POINTER(ffst_tuning)]),
         "ffst_tune": (I, [P, P, P, P, I, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double)]),
         "ffst_batch_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                   ctypes.POINTER(ffst_options), ctypes.POINTER(P)]),
@@ -246,6 +253,18 @@ def ffst_get_tuning(plan):
     b = ctypes.c_int()
     _check(load().ffst_get_tuning(plan, ctypes.byref(n), ctypes.byref(b)), "ffst_get_tuning")
     return n.value, b.value
+
+
+def ffst_set_tuning_ex(plan, nparts=0, blocks_per_cu=0, col_values=0, row_block=0):
+    t = ffst_tuning(int(nparts), int(blocks_per_cu), int(col_values), int(row_block))
+    _check(load().ffst_set_tuning_ex(plan, ctypes.byref(t)), "ffst_set_tuning_ex")
+
+
+def ffst_get_tuning_ex(plan):
+    """dict(nparts, blocks_per_cu, col_values, row_block) of a plan."""
+    t = ffst_tuning()
+    _check(load().ffst_get_tuning_ex(plan, ctypes.byref(t)), "ffst_get_tuning_ex")
+    return {k: getattr(t, k) for k, _ in ffst_tuning._fields_}
 
 
 def ffst_tune(plan, f_ptr, c_ptr, out_ptr, batch, ws_ptr, ws_size, stream_ptr):

@@ -123,7 +123,13 @@ class BatchPlan:
         _lib.ffst_batch_tune(self._h, f.data_ptr(), c.data_ptr(), y.data_ptr(), self.workspace(), self._stream())
 
     def class_tuning(self):
-        return [_lib.ffst_get_tuning(_lib.ffst_batch_class(self._h, c)[0]) for c in range(self.classes)]
+        """Per size class: dict(M, N, J, nparts, blocks_per_cu, col_values, row_block)."""
+        out = []
+        for c in range(self.classes):
+            h = _lib.ffst_batch_class(self._h, c)[0]
+            M, N, J, _ = _lib.ffst_plan_info(h)
+            out.append(dict(M=M, N=N, J=J, **_lib.ffst_get_tuning_ex(h)))
+        return out
 
     def close(self):
         if self._h:

@@ -55,6 +55,8 @@ struct ffst_plan {
   long long chunk_elems = 0;    // target size of one unit's compact buffer
   int tune_nparts = 0;          // adjoint partial sums per line (0: heuristic)
   int tune_blocks_per_cu = 0;   // persistent blocks per CU (0: per-kernel default)
+  int tune_col_values = 0;      // values per lane of the column-line FFTs (0: default)
+  int tune_row_block = 0;       // row blocks of the row kernels (0/1: default height, 2: the alternative)
   unsigned magic = 0;
 };
 
@@ -415,10 +417,23 @@ int reject_kind(const ffst_plan* p, bool want_complex, const char* call) {
 
 // Applies a plan's persistent-grid setting to the launches of one call.
 struct TuningScope {
-  int saved;
-  explicit TuningScope(const ffst_plan* p) : saved(t_blocks_per_cu) { t_blocks_per_cu = p->tune_blocks_per_cu; }
-  ~TuningScope() { t_blocks_per_cu = saved; }
+  int saved_b, saved_v, saved_r;
+  explicit TuningScope(const ffst_plan* p)
+      : saved_b(t_blocks_per_cu), saved_v(t_col_values), saved_r(t_row_block) {
+    t_blocks_per_cu = p->tune_blocks_per_cu;
+    t_col_values = p->tune_col_values;
+    t_row_block = p->tune_row_block == 2 ? 2 : 1;
+  }
+  ~TuningScope() {
+    t_blocks_per_cu = saved_b;
+    t_col_values = saved_v;
+    t_row_block = saved_r;
+  }
 };
+
+// The launch shapes compiled for a plan's sizes besides the defaults.
+int alt_col_values_of(const ffst_plan* p) { return alt_col_values(p->M); }
+bool row_block_tunable_of(const ffst_plan* p) { return p->N % 2 == 0 && row_block_tunable(p->N / 2); }
 
 // Smallest cyclic range [lo, lo + K) (mod M) holding every nonzero value of
 // a column line: the complement of its longest cyclic run of zeros (the
@@ -1035,18 +1050,43 @@ int ffst_inverse_complex(const ffst_plan* p, const float* coeffs, float* f, int 
 
 int ffst_set_tuning(ffst_plan* p, int nparts, int blocks_per_cu) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
-  if (nparts < 0 || nparts > 8) return fail(FFST_EINVAL, "nparts must be in [0, 8] (got %d)", nparts);
-  if (blocks_per_cu < 0 || blocks_per_cu > 32)
-    return fail(FFST_EINVAL, "blocks_per_cu must be in [0, 32] (got %d)", blocks_per_cu);
-  p->tune_nparts = nparts;
-  p->tune_blocks_per_cu = blocks_per_cu;
-  return ok();
+  ffst_tuning t{nparts, blocks_per_cu, p->tune_col_values, p->tune_row_block};
+  return ffst_set_tuning_ex(p, &t);
 }
 
 int ffst_get_tuning(const ffst_plan* p, int* nparts, int* blocks_per_cu) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (nparts) *nparts = p->tune_nparts;
   if (blocks_per_cu) *blocks_per_cu = p->tune_blocks_per_cu;
+  return ok();
+}
+
+int ffst_set_tuning_ex(ffst_plan* p, const ffst_tuning* t) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (!t) return fail(FFST_EINVAL, "tuning must be non-NULL");
+  if (t->nparts < 0 || t->nparts > 8) return fail(FFST_EINVAL, "nparts must be in [0, 8] (got %d)", t->nparts);
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
+    return fail(FFST_EINVAL, "blocks_per_cu must be in [0, 32] (got %d)", t->blocks_per_cu);
+  const int alt = alt_col_values_of(p);
+  if (t->col_values != 0 && !(alt != 0 && t->col_values == alt) && t->col_values != col_values(p->M))
+    return fail(FFST_EINVAL, "col_values %d is not compiled for column length %d (default %d, alternative %d)",
+                t->col_values, p->M, col_values(p->M), alt);
+  if (t->row_block < 0 || t->row_block > 2 || (t->row_block == 2 && !row_block_tunable_of(p)))
+    return fail(FFST_EINVAL, "row_block %d is not available for row length %d", t->row_block, p->N);
+  p->tune_nparts = t->nparts;
+  p->tune_blocks_per_cu = t->blocks_per_cu;
+  p->tune_col_values = t->col_values == col_values(p->M) ? 0 : t->col_values;
+  p->tune_row_block = t->row_block == 2 ? 2 : 0;
+  return ok();
+}
+
+int ffst_get_tuning_ex(const ffst_plan* p, ffst_tuning* t) {
+  if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  if (!t) return fail(FFST_EINVAL, "tuning must be non-NULL");
+  t->nparts = p->tune_nparts;
+  t->blocks_per_cu = p->tune_blocks_per_cu;
+  t->col_values = p->tune_col_values ? p->tune_col_values : col_values(p->M);
+  t->row_block = p->tune_row_block == 2 ? 2 : 1;
   return ok();
 }
 
@@ -1066,43 +1106,60 @@ int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch
   }
   const int parts[] = {1, 2, 4, 8};
   const int per_cu[] = {0, 1, 2, 4, 8, 16};
-  const int saved_n = p->tune_nparts, saved_b = p->tune_blocks_per_cu;
+  const int alt = alt_col_values_of(p);
+  const int colv[] = {0, alt};
+  const int rows[] = {0, 2};
+  const int ncolv = alt ? 2 : 1, nrows = row_block_tunable_of(p) ? 2 : 1;
+  ffst_tuning saved{};
+  saved.nparts = p->tune_nparts;
+  saved.blocks_per_cu = p->tune_blocks_per_cu;
+  saved.col_values = p->tune_col_values;
+  saved.row_block = p->tune_row_block;
   double best = -1.0;
-  int best_n = saved_n, best_b = saved_b, st = FFST_OK;
-  for (int n : parts) {
-    for (int bc : per_cu) {
-      p->tune_nparts = n;
-      p->tune_blocks_per_cu = bc;
-      if (ws_bytes(p, batch) > ws_size) continue;
-      double t_min = -1.0;
-      for (int rep = 0; rep < 4 && st == FFST_OK; ++rep) {  // first run is a warm-up
-        (void)hipEventRecord(a, s);
-        st = fwd(p, f, coeffs, batch, ws, stream);
-        if (st == FFST_OK) st = adj(p, coeffs, out, batch, ws, stream);
-        (void)hipEventRecord(b, s);
-        float ms = 0.f;
-        if (st == FFST_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
-          st = fail(FFST_EDEVICE, "ffst_tune: event timing failed");
-        if (st == FFST_OK && rep > 0 && (t_min < 0 || ms < t_min)) t_min = ms;
+  ffst_tuning best_t = saved;
+  int st = FFST_OK;
+  for (int iv = 0; iv < ncolv && st == FFST_OK; ++iv)
+    for (int ir = 0; ir < nrows && st == FFST_OK; ++ir)
+      for (int n : parts) {
+        for (int bc : per_cu) {
+          p->tune_nparts = n;
+          p->tune_blocks_per_cu = bc;
+          p->tune_col_values = colv[iv];
+          p->tune_row_block = rows[ir];
+          if (ws_bytes(p, batch) > ws_size) continue;
+          double t_min = -1.0;
+          for (int rep = 0; rep < 4 && st == FFST_OK; ++rep) {  // first run is a warm-up
+            (void)hipEventRecord(a, s);
+            st = fwd(p, f, coeffs, batch, ws, stream);
+            if (st == FFST_OK) st = adj(p, coeffs, out, batch, ws, stream);
+            (void)hipEventRecord(b, s);
+            float ms = 0.f;
+            if (st == FFST_OK &&
+                (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+              st = fail(FFST_EDEVICE, "ffst_tune: event timing failed");
+            if (st == FFST_OK && rep > 0 && (t_min < 0 || ms < t_min)) t_min = ms;
+          }
+          if (st != FFST_OK) break;
+          if (best < 0 || t_min < best) {
+            best = t_min;
+            best_t = ffst_tuning{n, bc, colv[iv], rows[ir]};
+          }
+        }
+        if (st != FFST_OK) break;
       }
-      if (st != FFST_OK) break;
-      if (best < 0 || t_min < best) {
-        best = t_min;
-        best_n = n;
-        best_b = bc;
-      }
-    }
-    if (st != FFST_OK) break;
-  }
   release_event(a);
   release_event(b);
   if (st != FFST_OK || best < 0) {
-    p->tune_nparts = saved_n;
-    p->tune_blocks_per_cu = saved_b;
+    p->tune_nparts = saved.nparts;
+    p->tune_blocks_per_cu = saved.blocks_per_cu;
+    p->tune_col_values = saved.col_values;
+    p->tune_row_block = saved.row_block;
     return st != FFST_OK ? st : fail(FFST_EINVAL, "ffst_tune: workspace too small for every candidate");
   }
-  p->tune_nparts = best_n;
-  p->tune_blocks_per_cu = best_b;
+  p->tune_nparts = best_t.nparts;
+  p->tune_blocks_per_cu = best_t.blocks_per_cu;
+  p->tune_col_values = best_t.col_values;
+  p->tune_row_block = best_t.row_block;
   if (best_ms) *best_ms = best;
   return ok();
 }

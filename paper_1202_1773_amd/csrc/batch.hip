@@ -354,8 +354,8 @@ int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, vo
   // Every class is tuned on its own; the classes then run side by side, so
   // the tuned settings are kept only if the whole batch is faster with them.
   const size_t nc = b->plans.size();
-  std::vector<int> saved_n(nc), saved_b(nc);
-  for (size_t c = 0; c < nc; ++c) ffst_get_tuning(b->plans[c], &saved_n[c], &saved_b[c]);
+  std::vector<ffst_tuning> saved(nc);
+  for (size_t c = 0; c < nc; ++c) ffst_get_tuning_ex(b->plans[c], &saved[c]);
   double before = 0.0, after = 0.0;
   int st = time_batch(b, f, coeffs, out, ws, stream, &before);
   drop_graphs(b);
@@ -365,7 +365,7 @@ int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, vo
   drop_graphs(b);
   if (st == FFST_OK) st = time_batch(b, f, coeffs, out, ws, stream, &after);
   if (st != FFST_OK || after > before) {
-    for (size_t c = 0; c < nc; ++c) ffst_set_tuning(b->plans[c], saved_n[c], saved_b[c]);
+    for (size_t c = 0; c < nc; ++c) ffst_set_tuning_ex(b->plans[c], &saved[c]);
     drop_graphs(b);
   }
   return st;

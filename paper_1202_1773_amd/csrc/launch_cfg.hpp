@@ -89,14 +89,44 @@ __host__ __device__ constexpr int row_block_rows(int GS) {
   return GS <= 16 ? 256 / GS : (GS <= 32 ? 16 : pow2_floor(512 / GS));
 }
 
-// Real rows of length N = 2L (complex FFT of length L), RB rows per block.
-template <int L>
+// Tunable launch shapes (set per call from the plan, read by the launchers):
+// the values per lane of the column-line FFTs (0: col_values(M); otherwise
+// alt_col_values(M), where compiled) and the height of the row blocks (1:
+// row_block_rows; 2: alt_block_rows, where compiled).
+inline thread_local int t_col_values = 0;
+inline thread_local int t_row_block = 1;
+
+// The second lane width compiled for column lines of length L: 16 for the
+// powers of two that use 8 (and 8 where 16 is the default), 6 for 3 * 2^k
+// from 96 on (radix 6 then 2s, against 12 then 4s); 0 where none is.
+__host__ __device__ constexpr int alt_col_values(int L) {
+  return (L & (L - 1)) == 0 ? (L >= 64 ? (L >= 1024 ? 8 : 16) : 0)
+                            : ((L % 3 == 0 && L % 9 != 0 && L >= 96 && ((L / 3) & (L / 3 - 1)) == 0) ? 6 : 0);
+}
+
+// Row lengths L (complex length N/2) whose kernels are also compiled with
+// the alternative row-block height: powers of two and 3 * 2^k from 32 on.
+__host__ __device__ constexpr bool row_block_tunable(int L) {
+  return L >= 32 && (((L & (L - 1)) == 0) || (L % 3 == 0 && ((L / 3) & (L / 3 - 1)) == 0));
+}
+
+// The alternative row-block height: twice the default for rows of up to 16
+// lane slots (a 512-thread block), half of it for wider rows, whose default
+// block has 512 threads already (doubling would cap the registers at 128 and
+// spill).
+__host__ __device__ constexpr int alt_block_rows(int GS) {
+  return GS <= 16 ? 2 * row_block_rows(GS) : (row_block_rows(GS) >= 2 ? row_block_rows(GS) / 2 : 1);
+}
+
+// Real rows of length N = 2L (complex FFT of length L), RB rows per block
+// (RBM = 2: the alternative height).
+template <int L, int RBM = 1>
 struct RowCfg {
   static constexpr int V = line_values(L);
   static constexpr int G = L / V;                      // lanes per row
   static constexpr int GS = group_slots(G);            // lane slots per row
   static constexpr int SYNC = GS <= 64 ? kWave : kBlock;
-  static constexpr int RB = row_block_rows(GS);
+  static constexpr int RB = RBM == 2 ? alt_block_rows(GS) : row_block_rows(GS);
   static constexpr int THREADS = RB * GS;
   static constexpr int STRIDE = lds_stride(L, V);
   // wave-level sync needs groups that tile wavefronts exactly
@@ -118,10 +148,11 @@ struct CRowCfg {
   static_assert(THREADS <= 1024, "row block too large");
 };
 
-// Contiguous lines of length L (the column direction, L = M).
-template <int L>
+// Contiguous lines of length L (the column direction, L = M); VV != 0
+// replaces the default values per lane.
+template <int L, int VV = 0>
 struct LineCfg {
-  static constexpr int V = col_values(L);
+  static constexpr int V = VV ? VV : col_values(L);
   static constexpr int G = L / V;
   static constexpr int GS = group_slots(G);
   static constexpr int SYNC = GS <= 64 ? kWave : kBlock;

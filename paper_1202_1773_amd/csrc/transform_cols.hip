@@ -15,12 +15,12 @@ namespace {
 // `nparts` partial arrays (parts + p * part_stride), added in order
 // p = 0, 1, ...; a separate instantiation, so that the plain transform keeps
 // its registers.
-template <int M, bool INV, bool PARTS>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_line_fft(float2* __restrict__ F, int nlines, int pitch,
-                                                                  const float2* __restrict__ parts, int nparts,
-                                                                  long long part_stride,
-                                                                  const float2* __restrict__ twM) {
-  using C = LineCfg<M>;
+template <int M, int VV, bool INV, bool PARTS>
+__global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_line_fft(float2* __restrict__ F, int nlines, int pitch,
+                                                                      const float2* __restrict__ parts, int nparts,
+                                                                      long long part_stride,
+                                                                      const float2* __restrict__ twM) {
+  using C = LineCfg<M, VV>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
@@ -89,9 +89,9 @@ __device__ __forceinline__ int hull_index(int e, int r_lo) {
 
 // Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image);
 // Psi_i[c] and F[c] are read only inside the line's hull (zero elsewhere).
-template <int M>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines(FwdLineJob job) {
-  using C = LineCfg<M>;
+template <int M, int VV>
+__global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_lines(FwdLineJob job) {
+  using C = LineCfg<M, VV>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
@@ -166,9 +166,9 @@ struct AdjLineJob {
 // Line (img, c, part): sum_i Psi_i[c] * fft_col(Z_i[c - lo_i]) over the spectra
 // of column c (part p takes every nparts-th of them); FUSED: scale, inverse
 // FFT and store A[c].
-template <int M, bool FUSED>
+template <int M, int VV, bool FUSED>
 __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
-  using C = LineCfg<M>;
+  using C = LineCfg<M, VV>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
@@ -259,10 +259,53 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
 // The compiler's own register allocation (no occupancy target): capping
 // the 512-point body at 128 registers (4 waves per SIMD) spilled to scratch
 // and was slower than 3 waves without spills.
-template <int M, bool FUSED>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_adj_lines(AdjLineJob job) {
-  adj_lines_body<M, FUSED>(job);
+template <int M, int VV, bool FUSED>
+__global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_adj_lines(AdjLineJob job) {
+  adj_lines_body<M, VV, FUSED>(job);
 }
+
+// Launches with the default lane width (VV = 0) or, when the call's tuning
+// asks for it and it is compiled, the alternative one.
+template <int n, int VV>
+hipError_t line_fft_with(float2* F, int nlines, int pitch, bool inverse, const float2* parts, int nparts,
+                         long long part_stride, const float2* twM, hipStream_t s) {
+  using C = LineCfg<n, VV>;
+  const long long units = (nlines + C::LPB - 1) / C::LPB;
+  const dim3 grid(grid_for(units, C::THREADS)), block(C::THREADS);
+  if (inverse && nparts > 0)
+    hipLaunchKernelGGL((k_line_fft<n, VV, true, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts,
+                       part_stride, twM);
+  else if (inverse)
+    hipLaunchKernelGGL((k_line_fft<n, VV, true, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts,
+                       part_stride, twM);
+  else
+    hipLaunchKernelGGL((k_line_fft<n, VV, false, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts,
+                       part_stride, twM);
+  return hipGetLastError();
+}
+
+template <int n, int VV>
+hipError_t fwd_lines_with(const FwdLineJob& job, long long total, hipStream_t s) {
+  using C = LineCfg<n, VV>;
+  const long long units = (total + C::LPB - 1) / C::LPB;
+  hipLaunchKernelGGL((k_fwd_lines<n, VV>), dim3(grid_for(units, C::THREADS)), dim3(C::THREADS), 0, s, job);
+  return hipGetLastError();
+}
+
+template <int n, int VV>
+hipError_t adj_lines_with(const AdjLineJob& job, long long total, bool fused, hipStream_t s) {
+  using C = LineCfg<n, VV>;
+  const long long units = (total + C::LPB - 1) / C::LPB;
+  const dim3 grid(grid_for(units, C::THREADS)), block(C::THREADS);
+  if (fused)
+    hipLaunchKernelGGL((k_adj_lines<n, VV, true>), grid, block, 0, s, job);
+  else
+    hipLaunchKernelGGL((k_adj_lines<n, VV, false>), grid, block, 0, s, job);
+  return hipGetLastError();
+}
+
+// true when this call's tuning asks for the alternative lane width of n
+inline bool alt_cols_requested(int n) { return t_col_values != 0 && t_col_values == alt_col_values(n); }
 
 // Line kernels take the length M: every 2^a 3^b from 4 to 4096.
 #define FFST_COL_CASES(X) X(4) X(6) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
@@ -286,21 +329,12 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
                            long long part_stride, const float2* twM, hipStream_t s) {
   if (nlines == 0) return hipSuccess;
   switch (M) {
-#define CASE(n)                                                                                   \
-  case n: {                                                                                       \
-    const long long units = (nlines + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                     \
-    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if (inverse && nparts > 0)                                                                    \
-      hipLaunchKernelGGL((k_line_fft<n, true, true>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
-                         part_stride, twM);                                                       \
-    else if (inverse)                                                                             \
-      hipLaunchKernelGGL((k_line_fft<n, true, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
-                         part_stride, twM);                                                       \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_line_fft<n, false, false>), grid, block, 0, s, F, nlines, pitch, parts, nparts, \
-                         part_stride, twM);                                                       \
-    return hipGetLastError();                                                                     \
-  }
+#define CASE(n)                                                                                        \
+  case n:                                                                                              \
+    if constexpr (alt_col_values(n) != 0)                                                             \
+      if (alt_cols_requested(n))                                                                       \
+        return line_fft_with<n, alt_col_values(n)>(F, nlines, pitch, inverse, parts, nparts, part_stride, twM, s); \
+    return line_fft_with<n, 0>(F, nlines, pitch, inverse, parts, nparts, part_stride, twM, s);
     FFST_COL_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -314,12 +348,10 @@ hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
   const long long total = (long long)job.nlines * job.nimg;
   switch (a.M) {
 #define CASE(n)                                                                                   \
-  case n: {                                                                                       \
-    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
-    hipLaunchKernelGGL(k_fwd_lines<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),                \
-                       dim3(LineCfg<n>::THREADS), 0, s, job);                                     \
-    return hipGetLastError();                                                                     \
-  }
+  case n:                                                                                         \
+    if constexpr (alt_col_values(n) != 0)                                                        \
+      if (alt_cols_requested(n)) return fwd_lines_with<n, alt_col_values(n)>(job, total, s);      \
+    return fwd_lines_with<n, 0>(job, total, s);
     FFST_COL_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -333,15 +365,10 @@ hipError_t launch_adj_lines(const AdjLineArgs& a, hipStream_t s) {
   const long long total = (long long)job.H * job.nimg * job.nparts;
   switch (a.M) {
 #define CASE(n)                                                                                   \
-  case n: {                                                                                       \
-    const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
-    const dim3 grid(grid_for(units, LineCfg<n>::THREADS)), block(LineCfg<n>::THREADS);            \
-    if (a.fused)                                                                                  \
-      hipLaunchKernelGGL((k_adj_lines<n, true>), grid, block, 0, s, job);                         \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_adj_lines<n, false>), grid, block, 0, s, job);                        \
-    return hipGetLastError();                                                                     \
-  }
+  case n:                                                                                         \
+    if constexpr (alt_col_values(n) != 0)                                                        \
+      if (alt_cols_requested(n)) return adj_lines_with<n, alt_col_values(n)>(job, total, a.fused, s); \
+    return adj_lines_with<n, 0>(job, total, a.fused, s);
     FFST_COL_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

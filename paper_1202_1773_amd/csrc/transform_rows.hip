@@ -70,9 +70,9 @@ __device__ __forceinline__ float2 sign_times(float2 v, float s) {
 //
 // SIGN (k_r2c_rows_sign): the rows are read as s * sign(x), the subgradient of
 // s * ||x||_1, so that the adjoint of an l1 term needs no extra pass.
-template <int L, bool SMALL, bool SIGN>
+template <int L, int RBM, bool SMALL, bool SIGN>
 __device__ __forceinline__ void r2c_rows_body(const RowJob& job) {
-  using C = RowCfg<L>;
+  using C = RowCfg<L, RBM>;
   constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
   __shared__ float2 lds[C::RB * C::STRIDE];
   const int g = group_index<C>();          // row slot (FFT phase)
@@ -141,19 +141,19 @@ __device__ __forceinline__ void r2c_rows_body(const RowJob& job) {
   }
 }
 
-template <int L, bool SMALL>
-__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows(RowJob job) {
-  r2c_rows_body<L, SMALL, false>(job);
+template <int L, int RBM, bool SMALL>
+__global__ void __launch_bounds__((RowCfg<L, RBM>::THREADS)) k_r2c_rows(RowJob job) {
+  r2c_rows_body<L, RBM, SMALL, false>(job);
 }
 
-template <int L, bool SMALL>
-__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_r2c_rows_sign(RowJob job) {
-  r2c_rows_body<L, SMALL, true>(job);
+template <int L, int RBM, bool SMALL>
+__global__ void __launch_bounds__((RowCfg<L, RBM>::THREADS)) k_r2c_rows_sign(RowJob job) {
+  r2c_rows_body<L, RBM, SMALL, true>(job);
 }
 
-template <int L, bool SMALL>
-__global__ void __launch_bounds__(RowCfg<L>::THREADS) k_c2r_rows(RowJob job) {
-  using C = RowCfg<L>;
+template <int L, int RBM, bool SMALL>
+__global__ void __launch_bounds__((RowCfg<L, RBM>::THREADS)) k_c2r_rows(RowJob job) {
+  using C = RowCfg<L, RBM>;
   constexpr int V = C::V, G = C::G, N = 2 * L, NT = C::THREADS;
   // values each thread moves in the transposed load: k = tc + STEP m, k <= L
   constexpr int STEP = NT / C::RB;
@@ -458,25 +458,47 @@ static hipError_t launch_rows_odd(const RowArgs& a, bool inverse, hipStream_t s)
   }
 }
 
+// Launchers with the default row blocks (RBM = 1) or, when the call's tuning
+// asks for it and the length is compiled for it, doubled ones.
+template <int n, int RBM>
+hipError_t r2c_rows_with(const RowArgs& a, hipStream_t s) {
+  using C = RowCfg<n, RBM>;
+  const RowJob job = make_row_job(a, C::RB);
+  const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);
+  const dim3 grid(grid_for(units, C::THREADS)), block(C::THREADS);
+  if (job.sign_scale && job.rb < C::RB)
+    hipLaunchKernelGGL((k_r2c_rows_sign<n, RBM, true>), grid, block, 0, s, job);
+  else if (job.sign_scale)
+    hipLaunchKernelGGL((k_r2c_rows_sign<n, RBM, false>), grid, block, 0, s, job);
+  else if (job.rb < C::RB)
+    hipLaunchKernelGGL((k_r2c_rows<n, RBM, true>), grid, block, 0, s, job);
+  else
+    hipLaunchKernelGGL((k_r2c_rows<n, RBM, false>), grid, block, 0, s, job);
+  return hipGetLastError();
+}
+
+template <int n, int RBM>
+hipError_t c2r_rows_with(const RowArgs& a, hipStream_t s) {
+  using C = RowCfg<n, RBM>;
+  const RowJob job = make_row_job(a, C::RB);
+  const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);
+  const dim3 grid(grid_for(units, C::THREADS)), block(C::THREADS);
+  if (job.rb < C::RB)
+    hipLaunchKernelGGL((k_c2r_rows<n, RBM, true>), grid, block, 0, s, job);
+  else
+    hipLaunchKernelGGL((k_c2r_rows<n, RBM, false>), grid, block, 0, s, job);
+  return hipGetLastError();
+}
+
 hipError_t launch_r2c_rows(const RowArgs& a, hipStream_t s) {
   if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
   if (a.N % 2) return launch_rows_odd(a, false, s);
   switch (a.N / 2) {
-#define CASE(n)                                                                                   \
-  case n: {                                                                                       \
-    const RowJob job = make_row_job(a, RowCfg<n>::RB);                                            \
-    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
-    const dim3 grid(grid_for(units, RowCfg<n>::THREADS)), block(RowCfg<n>::THREADS);             \
-    if (job.sign_scale && job.rb < RowCfg<n>::RB)                                                 \
-      hipLaunchKernelGGL((k_r2c_rows_sign<n, true>), grid, block, 0, s, job);                         \
-    else if (job.sign_scale)                                                                      \
-      hipLaunchKernelGGL((k_r2c_rows_sign<n, false>), grid, block, 0, s, job);                        \
-    else if (job.rb < RowCfg<n>::RB)                                                              \
-      hipLaunchKernelGGL((k_r2c_rows<n, true>), grid, block, 0, s, job);                              \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_r2c_rows<n, false>), grid, block, 0, s, job);                             \
-    return hipGetLastError();                                                                     \
-  }
+#define CASE(n)                                                                    \
+  case n:                                                                          \
+    if constexpr (row_block_tunable(n))                                            \
+      if (t_row_block == 2) return r2c_rows_with<n, 2>(a, s);                      \
+    return r2c_rows_with<n, 1>(a, s);
     FFST_ROW_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -487,17 +509,11 @@ hipError_t launch_c2r_rows(const RowArgs& a, hipStream_t s) {
   if (a.nimg == 0 || a.nplanes == 0) return hipSuccess;
   if (a.N % 2) return launch_rows_odd(a, true, s);
   switch (a.N / 2) {
-#define CASE(n)                                                                                   \
-  case n: {                                                                                       \
-    const RowJob job = make_row_job(a, RowCfg<n>::RB);                                            \
-    const long long units = (long long)a.nimg * a.nplanes * (a.M / job.rb);                       \
-    const dim3 grid(grid_for(units, RowCfg<n>::THREADS)), block(RowCfg<n>::THREADS);             \
-    if (job.rb < RowCfg<n>::RB)                                                                   \
-      hipLaunchKernelGGL((k_c2r_rows<n, true>), grid, block, 0, s, job);                              \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_c2r_rows<n, false>), grid, block, 0, s, job);                             \
-    return hipGetLastError();                                                                     \
-  }
+#define CASE(n)                                                                    \
+  case n:                                                                          \
+    if constexpr (row_block_tunable(n))                                            \
+      if (t_row_block == 2) return c2r_rows_with<n, 2>(a, s);                      \
+    return c2r_rows_with<n, 1>(a, s);
     FFST_ROW_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -120,9 +120,14 @@ class Plan:
         """(nparts, blocks_per_cu) of the plan; 0 means the built-in choice."""
         return _lib.ffst_get_tuning(self._h)
 
-    def set_tuning(self, nparts=0, blocks_per_cu=0):
-        _lib.ffst_set_tuning(self._h, nparts, blocks_per_cu)
+    def set_tuning(self, nparts=0, blocks_per_cu=0, col_values=0, row_block=0):
+        """Launch settings (ffst_tuning in include/ffst.h); 0 keeps a default."""
+        _lib.ffst_set_tuning_ex(self._h, nparts, blocks_per_cu, col_values, row_block)
         self._ws.clear()
+
+    def tuning_ex(self):
+        """All launch settings: dict(nparts, blocks_per_cu, col_values, row_block)."""
+        return _lib.ffst_get_tuning_ex(self._h)
 
     def tune(self, x):
         """Autotune the launch settings for forward + adjoint of the images x
@@ -132,7 +137,7 @@ class Plan:
         B = xb.shape[0]
         saved = self.tuning()
         _lib.ffst_set_tuning(self._h, 8, saved[1])        # largest workspace of any setting
-        ws_size = self.workspace_size(B)
+        ws_size = max(self.workspace_size(B), _lib.ffst_workspace_size(self._h, B))
         _lib.ffst_set_tuning(self._h, *saved)
         ws = torch.empty(ws_size + 256, dtype=torch.uint8, device=self.device)
         ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
