@@ -35,9 +35,8 @@ struct ffst_plan {
   long long* d_img_off = nullptr;
   int2* d_lines = nullptr;      // forward column lines (spectrum, column), by spectrum
   // real shearlets: every window column line of Psi_i over its cyclic nonzero
-  // hull (see FwdLineArgs), for the forward lines and the adjoint's CSR entries
+  // hull (see FwdColArgs), for the CSR entries of both column passes
   float* psic = nullptr;
-  int4* d_line_hull = nullptr;
   int4* d_col_hull = nullptr;
   int* d_col_ptr = nullptr;     // per plane group: columns -> spectra (CSR, absolute pointers)
   int* d_col_planes = nullptr;
@@ -256,7 +255,7 @@ void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
                   p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent,
-                  p->psic, p->d_line_hull, p->d_col_hull};
+                  p->psic, p->d_col_hull};
   for (void* b : bufs)
     if (b) release(b);
   p->magic = 0;
@@ -720,7 +719,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     }
   }
   std::vector<float> psic;
-  std::vector<int4> line_hull, col_hull;
+  std::vector<int4> col_hull;
   if (!cplx) {
     std::vector<int4> hull_of;
     std::vector<long long> hbase;
@@ -729,7 +728,6 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       return fail(e == hipErrorOutOfMemory ? FFST_ENOMEM : FFST_EDEVICE, "spectrum hulls: %s", hipGetErrorString(e));
     }
     auto hull = [&](int i, int c) { return hull_of[hbase[i] + (c - p->lo[i])]; };
-    for (const int2& l : lines) line_hull.push_back(hull(l.x, l.y));
     for (int g = 0; g < ngroups; ++g)
       for (int c = 0; c < p->H; ++c)
         for (int t = col_ptr[g * (p->H + 1) + c]; t < col_ptr[g * (p->H + 1) + c + 1]; ++t)
@@ -742,8 +740,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
       (e = upload(&p->d_lines, lines)) != hipSuccess || (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
       (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess ||
-      (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_line_hull, line_hull)) != hipSuccess ||
-      (e = upload(&p->d_col_hull, col_hull)) != hipSuccess) {
+      (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_col_hull, col_hull)) != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
@@ -839,12 +836,10 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
 
-  // F = fft2(f) on the half plane, column-contiguous
+  // row transforms of the images, column-contiguous; the column pass below
+  // completes fft2(f) column by column before multiplying by the spectra
   RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
   hipError_t e = timed(KID_R2C_IMAGE, s, [&] { return launch_r2c_rows(ra, s); });
-  if (e == hipSuccess)
-    e = timed(KID_FFT_COLS_IMAGE, s,
-              [&] { return launch_line_fft(p->M, F, batch * p->H, p->pitch, false, nullptr, 0, 0, p->twM, s); });
 
   const int ngroups = (int)p->groups.size() - 1;
   for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
@@ -853,10 +848,9 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
       const int p0 = p->groups[g], p1 = p->groups[g + 1];
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
-      FwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_line_hull + p->line_ptr[p0], p->d_lines + p->line_ptr[p0],
-                     p->line_ptr[p1] - p->line_ptr[p0], nimg, p->pitch, plane_windows(p), unit_stride, base, Y,
-                     scale, p->twM};
-      e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_lines(fa, s); });
+      FwdColArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_col_ptr + g * (p->H + 1), p->d_col_planes,
+                    p->d_col_hull, nimg, p->pitch, plane_windows(p), unit_stride, base, Y, scale, p->twM};
+      e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_cols(fa, s); });
       if (e != hipSuccess) break;
       RowArgs rc{coeffs + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
                  p->M, p->N, p->pitch, plane_windows(p), p->twN};

@@ -85,13 +85,19 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
 // Spectrum column lines over their cyclic nonzero hull: line (i, c) holds
 // Psi_i at rows (r_lo + m) mod M, m < K, at psic + off; elsewhere Psi_i is
 // zero on that column. A line's hull is the int4 (r_lo, K, off, 0).
-struct FwdLineArgs {
+//
+// Forward column pass: per (column c, image), the column FFT of the image's
+// row transforms F (not yet transformed along the columns), then for every
+// spectrum i of the plane group whose window holds c the inverse column FFT
+// of Psi_i[c] F[c] / (M N) into Y_i.
+struct FwdColArgs {
   int M, N;
-  const float2* F;          // [nimg][N/2+1][M]
+  const float2* F;          // row transforms, column-contiguous [nimg][N/2+1][pitch]
   const float* psic;        // compact spectrum lines
-  const int4* hull;         // per line: (r_lo, K, off, 0)
-  const int2* lines;        // (spectrum, column)
-  int nlines, nimg;
+  const int* col_ptr;       // CSR of the plane group: column -> spectra
+  const int* col_planes;
+  const int4* col_hull;     // hull of every CSR entry's line
+  int nimg;
   int pitch;                // complex elements between column lines of F and Y
   Windows win;
   long long y_img_stride, y_off_base;
@@ -99,14 +105,14 @@ struct FwdLineArgs {
   float scale;
   const float2* twM;
 };
-hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s);
+hipError_t launch_fwd_cols(const FwdColArgs& a, hipStream_t s);
 
 struct AdjLineArgs {
   int M, N;
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psic;        // compact spectrum lines
+  const float* psic;        // compact spectrum lines (see FwdColArgs)
   const int* col_ptr;
   const int* col_planes;
   const int4* col_hull;     // hull of (col_planes[t], column) for every CSR entry t

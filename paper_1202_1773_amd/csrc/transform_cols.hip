@@ -65,20 +65,6 @@ __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_line_fft(float2* 
   }
 }
 
-struct FwdLineJob {
-  const float2* F;          // [nimg][H][M]
-  const float* psic;        // compact spectrum lines (see FwdLineArgs)
-  const int4* hull;         // per line: (r_lo, K, off, 0)
-  const int2* lines;        // (spectrum, column) of the unit's lines
-  int nlines, nimg, H;
-  int pitch;                // complex elements between column lines of F and Y
-  Windows win;
-  long long y_img_stride, y_off_base;
-  float2* Y;
-  float scale;
-  const float2* twM;
-};
-
 // Index m of element e of a column line inside the line's cyclic hull
 // [r_lo, r_lo + K) (mod L), or a value >= K when e lies outside it.
 template <int L>
@@ -87,60 +73,72 @@ __device__ __forceinline__ int hull_index(int e, int r_lo) {
   return d < 0 ? d + L : d;
 }
 
-// Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]) for every (line, image);
-// Psi_i[c] and F[c] are read only inside the line's hull (zero elsewhere).
+struct FwdColJob {
+  const float2* F;          // row transforms of the images, column-contiguous [nimg][H][pitch]
+  const float* psic;        // compact spectrum lines (see FwdColArgs)
+  const int* col_ptr;       // CSR over columns -> spectra of this plane group
+  const int* col_planes;
+  const int4* col_hull;     // hull of every CSR entry's line
+  int H, nimg;
+  int pitch;                // complex elements between column lines of F and Y
+  Windows win;
+  long long y_img_stride, y_off_base;
+  float2* Y;
+  float scale;
+  const float2* twM;
+};
+
+// Unit (c, img): the column FFT of the image's row transforms at column c
+// gives F[c] (the image spectrum's column, kept in registers); then, for
+// every spectrum i whose window holds c,
+//   Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]),
+// with Psi_i[c] read only inside its hull. Units run column-major (images
+// of one column next to each other share the spectrum lines). The next
+// spectrum's line is loaded while the current one is transformed.
 template <int M, int VV>
-__global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_lines(FwdLineJob job) {
+__global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJob job) {
   using C = LineCfg<M, VV>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
   const int j = group_lane<C>();
+  float2* my = lds + g * C::STRIDE;
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
-  const int total = job.nlines * job.nimg;
-  // Units run image by image, lines ordered by column, so neighbouring units
-  // share F[c] (measured faster than running the images of one line side by
-  // side, which would share the Psi line instead). Software pipeline: the
-  // next unit's F and Psi lines are loaded while the current line is
-  // transformed.
-  float2 fn[V];
-  float pn[V];
-  auto load_unit = [&](int u) {
-    const int q = u * C::LPB + g;
-    const int qq = q < total ? q : 0;
-    const int img = qq / job.nlines;
-    const int li = qq % job.nlines;
-    const int2 ln = job.lines[li];
-    const int4 hl = job.hull[li];
-    const float2* fb = job.F + ((long long)img * job.H + ln.y) * job.pitch;
-    const float* pb = job.psic + hl.z;
-#pragma unroll
-    for (int s = 0; s < V; ++s) {
-      const int e = j + G * s;
-      const int m = hull_index<M>(e, hl.x);
-      const bool in = m < hl.y;
-      fn[s] = in ? fb[e] : make_float2(0.f, 0.f);
-      pn[s] = in ? pb[m] : 0.f;
-    }
-  };
-  int u = blockIdx.x;
-  if (u * C::LPB < total) load_unit(u);
-  for (; u * C::LPB < total; u += gridDim.x) {
+  const int total = job.H * job.nimg;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
     const int q = u * C::LPB + g;
     const bool ok = q < total;
     const int qq = ok ? q : 0;
-    const int img = qq / job.nlines;
-    const int2 ln = job.lines[qq % job.nlines];
-    const int i = ln.x, c = ln.y;
-    float2 v[V];
+    const int img = qq % job.nimg;
+    const int c = qq / job.nimg;
+    const float2* fb = job.F + ((long long)img * job.H + c) * job.pitch;
+    float2 f[V];
 #pragma unroll
-    for (int s = 0; s < V; ++s) v[s] = cscale(fn[s], pn[s] * job.scale);
-    if ((u + (int)gridDim.x) * C::LPB < total) load_unit(u + gridDim.x);
-    fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
-    if (ok) {
-      float2* yb = job.Y + img * job.y_img_stride + (job.win.off[i] - job.y_off_base) +
-                   (long long)(c - job.win.lo[i]) * job.pitch;
+    for (int s = 0; s < V; ++s) f[s] = fb[j + G * s];
+    fft_group<M, V, false, C::SYNC>(f, j, my, tw);
+    float2* yimg = job.Y + img * job.y_img_stride - job.y_off_base;
+    const int q1 = ok ? job.col_ptr[c + 1] : 0;
+    int t = job.col_ptr[c];
+    float pn[V];
+    auto load_psi = [&](int tt) {
+      const int4 hl = job.col_hull[tt];
+      const float* pb = job.psic + hl.z;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        const int m = hull_index<M>(j + G * s, hl.x);
+        pn[s] = m < hl.y ? pb[m] * job.scale : 0.f;
+      }
+    };
+    if (t < q1) load_psi(t);
+    for (; t < q1; ++t) {
+      const int i = job.col_planes[t];
+      float2 v[V];
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cscale(f[s], pn[s]);
+      if (t + 1 < q1) load_psi(t + 1);
+      fft_group<M, V, true, C::SYNC>(v, j, my, tw);
+      float2* yb = yimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
 #pragma unroll
       for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
     }
@@ -151,7 +149,7 @@ struct AdjLineJob {
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psic;        // compact spectrum lines (see FwdLineArgs)
+  const float* psic;        // compact spectrum lines (see FwdColArgs)
   const int* col_ptr;       // CSR over columns -> spectra of this plane group
   const int* col_planes;
   const int4* col_hull;     // hull of every CSR entry's line
@@ -285,10 +283,10 @@ hipError_t line_fft_with(float2* F, int nlines, int pitch, bool inverse, const f
 }
 
 template <int n, int VV>
-hipError_t fwd_lines_with(const FwdLineJob& job, long long total, hipStream_t s) {
+hipError_t fwd_cols_with(const FwdColJob& job, long long total, hipStream_t s) {
   using C = LineCfg<n, VV>;
   const long long units = (total + C::LPB - 1) / C::LPB;
-  hipLaunchKernelGGL((k_fwd_lines<n, VV>), dim3(grid_for(units, C::THREADS)), dim3(C::THREADS), 0, s, job);
+  hipLaunchKernelGGL((k_fwd_cols<n, VV>), dim3(grid_for(units, C::THREADS)), dim3(C::THREADS), 0, s, job);
   return hipGetLastError();
 }
 
@@ -341,17 +339,17 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
   }
 }
 
-hipError_t launch_fwd_lines(const FwdLineArgs& a, hipStream_t s) {
-  FwdLineJob job{a.F, a.psic, a.hull, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.pitch, a.win, a.y_img_stride,
-                 a.y_off_base, a.Y, a.scale, a.twM};
-  if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
-  const long long total = (long long)job.nlines * job.nimg;
+hipError_t launch_fwd_cols(const FwdColArgs& a, hipStream_t s) {
+  FwdColJob job{a.F, a.psic, a.col_ptr, a.col_planes, a.col_hull, a.N / 2 + 1, a.nimg, a.pitch, a.win,
+                a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
+  if (job.nimg == 0) return hipSuccess;
+  const long long total = (long long)job.H * job.nimg;
   switch (a.M) {
 #define CASE(n)                                                                                   \
   case n:                                                                                         \
     if constexpr (alt_col_values(n) != 0)                                                        \
-      if (alt_cols_requested(n)) return fwd_lines_with<n, alt_col_values(n)>(job, total, s);      \
-    return fwd_lines_with<n, 0>(job, total, s);
+      if (alt_cols_requested(n)) return fwd_cols_with<n, alt_col_values(n)>(job, total, s);      \
+    return fwd_cols_with<n, 0>(job, total, s);
     FFST_COL_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
