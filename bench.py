@@ -321,6 +321,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-batch and complex-shearlet measurements")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch settings only")
+    ap.add_argument("--tuning", default=None, metavar="NPARTS,BLOCKS_PER_CU,COL_VALUES,ROW_BLOCK",
+                    help="use these launch settings for the batched and plain plans instead of autotuning "
+                         "(ffst_tuning in include/ffst.h; for profiling runs that must not sweep)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -351,7 +354,12 @@ def main():
     c1 = torch.empty((eta, M, N), dtype=torch.float32, device=dev)
     y1 = torch.empty((M, N), dtype=torch.float32, device=dev)
     tuning = None
-    if not args.no_tune:
+    if args.tuning:
+        vals = [int(v) for v in args.tuning.split(",")]
+        for p_ in (plan, plan1):
+            p_.set_tuning(*vals)
+        tuning = {"batched": plan.tuning_ex(), "plain": plan1.tuning_ex(), "given": True}
+    elif not args.no_tune:
         # launch settings picked by the autotuner, per plan, before any timing
         plan.tune(x)
         plan1.tune(x[0])

@@ -237,8 +237,12 @@ int ffst_inverse_complex(const ffst_plan* plan, const float* coeffs, float* f, i
 /*
  * Launch tuning of a plan (runtime knobs only; no setting changes what is
  * computed beyond the order of the adjoint's floating-point sums):
- *   nparts        number of partial sums the adjoint splits the sum over the
- *                 spectra of a column into (1 .. 8; 0 = chosen from the batch)
+ *   nparts        number of lines the spectra of one column (of one image) are
+ *                 spread over in the column passes (1 .. 8; 0 = chosen from
+ *                 the batch): in the forward every line repeats the column's
+ *                 FFT of the image spectrum and runs every nparts-th spectrum,
+ *                 in the adjoint every line forms a partial sum, and the
+ *                 partial sums are added in a fixed order
  *   blocks_per_cu persistent workgroups per compute unit of every kernel
  *                 (1 .. 32; 0 = each kernel's default)
  * The workspace size depends on nparts: query ffst_workspace_size after

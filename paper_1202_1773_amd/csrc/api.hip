@@ -52,7 +52,7 @@ struct ffst_plan {
   std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
   std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
   long long chunk_elems = 0;    // target size of one unit's compact buffer
-  int tune_nparts = 0;          // adjoint partial sums per line (0: heuristic)
+  int tune_nparts = 0;          // lines per column in the column passes (0: heuristic)
   int tune_blocks_per_cu = 0;   // persistent blocks per CU (0: per-kernel default)
   int tune_col_values = 0;      // values per lane of the column-line FFTs (0: default)
   int tune_row_block = 0;       // row blocks of the row kernels (0/1: default height, 2: the alternative)
@@ -269,7 +269,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // adjoint's sum over spectra is spread over blocks.
 struct Schedule {
   int chunk_imgs = 1;     // images per unit
-  int nparts = 1;         // adjoint partial sums per (image, tile)
+  int nparts = 1;         // lines per (image, column) in the column passes (adjoint: partial sums)
   bool fused = true;      // adjoint column pass ends with its inverse FFT
   size_t fa_bytes = 0, yz_bytes = 0, part_bytes = 0;
 };
@@ -849,7 +849,8 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
       FwdColArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_col_ptr + g * (p->H + 1), p->d_col_planes,
-                    p->d_col_hull, nimg, p->pitch, plane_windows(p), unit_stride, base, Y, scale, p->twM};
+                    p->d_col_hull, nimg, sc.nparts, p->pitch, plane_windows(p), unit_stride, base, Y, scale,
+                    p->twM};
       e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_cols(fa, s); });
       if (e != hipSuccess) break;
       RowArgs rc{coeffs + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,

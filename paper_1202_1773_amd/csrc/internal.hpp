@@ -86,10 +86,10 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
 // Psi_i at rows (r_lo + m) mod M, m < K, at psic + off; elsewhere Psi_i is
 // zero on that column. A line's hull is the int4 (r_lo, K, off, 0).
 //
-// Forward column pass: per (column c, image), the column FFT of the image's
-// row transforms F (not yet transformed along the columns), then for every
-// spectrum i of the plane group whose window holds c the inverse column FFT
-// of Psi_i[c] F[c] / (M N) into Y_i.
+// Forward column pass: per (column c, image, part), the column FFT of the
+// image's row transforms F (not yet transformed along the columns), then for
+// every nparts-th spectrum i of the plane group whose window holds c the
+// inverse column FFT of Psi_i[c] F[c] / (M N) into Y_i.
 struct FwdColArgs {
   int M, N;
   const float2* F;          // row transforms, column-contiguous [nimg][N/2+1][pitch]
@@ -97,7 +97,7 @@ struct FwdColArgs {
   const int* col_ptr;       // CSR of the plane group: column -> spectra
   const int* col_planes;
   const int4* col_hull;     // hull of every CSR entry's line
-  int nimg;
+  int nimg, nparts;         // nparts: lines per column sharing its spectra
   int pitch;                // complex elements between column lines of F and Y
   Windows win;
   long long y_img_stride, y_off_base;

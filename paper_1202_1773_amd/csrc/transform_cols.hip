@@ -7,6 +7,8 @@
 #include "internal.hpp"
 #include "launch_cfg.hpp"
 
+#include <algorithm>
+
 namespace ffst {
 namespace {
 
@@ -79,7 +81,7 @@ struct FwdColJob {
   const int* col_ptr;       // CSR over columns -> spectra of this plane group
   const int* col_planes;
   const int4* col_hull;     // hull of every CSR entry's line
-  int H, nimg;
+  int H, nimg, nparts;
   int pitch;                // complex elements between column lines of F and Y
   Windows win;
   long long y_img_stride, y_off_base;
@@ -88,13 +90,16 @@ struct FwdColJob {
   const float2* twM;
 };
 
-// Unit (c, img): the column FFT of the image's row transforms at column c
-// gives F[c] (the image spectrum's column, kept in registers); then, for
-// every spectrum i whose window holds c,
+// Unit (c, img, part): the column FFT of the image's row transforms at
+// column c gives F[c] (the image spectrum's column, kept in registers);
+// then, for every nparts-th spectrum i whose window holds c (starting at
+// the part's index),
 //   Y_i[c - lo_i] = ifft_col(Psi_i[c] * scale * F[c]),
-// with Psi_i[c] read only inside its hull. Units run column-major (images
-// of one column next to each other share the spectrum lines). The next
-// spectrum's line is loaded while the current one is transformed.
+// with Psi_i[c] read only inside its hull. Several parts per column (small
+// batches) repeat the column FFT so that a column's spectra run on several
+// lines in parallel. Units run column-major (images of one column next to
+// each other share the spectrum lines). The next spectrum's line is loaded
+// while the current one is transformed.
 template <int M, int VV>
 __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJob job) {
   using C = LineCfg<M, VV>;
@@ -105,13 +110,15 @@ __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJo
   float2* my = lds + g * C::STRIDE;
   TwiddleRegs<M, V> tw;
   tw.load(j, job.twM, 1);
-  const int total = job.H * job.nimg;
+  const int total = job.H * job.nimg * job.nparts;
   for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
     const int q = u * C::LPB + g;
     const bool ok = q < total;
     const int qq = ok ? q : 0;
-    const int img = qq % job.nimg;
-    const int c = qq / job.nimg;
+    const int part = qq % job.nparts;
+    const int rest = qq / job.nparts;
+    const int img = rest % job.nimg;
+    const int c = rest / job.nimg;
     const float2* fb = job.F + ((long long)img * job.H + c) * job.pitch;
     float2 f[V];
 #pragma unroll
@@ -119,7 +126,7 @@ __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJo
     fft_group<M, V, false, C::SYNC>(f, j, my, tw);
     float2* yimg = job.Y + img * job.y_img_stride - job.y_off_base;
     const int q1 = ok ? job.col_ptr[c + 1] : 0;
-    int t = job.col_ptr[c];
+    int t = job.col_ptr[c] + part;
     float pn[V];
     auto load_psi = [&](int tt) {
       const int4 hl = job.col_hull[tt];
@@ -131,12 +138,12 @@ __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJo
       }
     };
     if (t < q1) load_psi(t);
-    for (; t < q1; ++t) {
+    for (; t < q1; t += job.nparts) {
       const int i = job.col_planes[t];
       float2 v[V];
 #pragma unroll
       for (int s = 0; s < V; ++s) v[s] = cscale(f[s], pn[s]);
-      if (t + 1 < q1) load_psi(t + 1);
+      if (t + job.nparts < q1) load_psi(t + job.nparts);
       fft_group<M, V, true, C::SYNC>(v, j, my, tw);
       float2* yb = yimg + job.win.off[i] + (long long)(c - job.win.lo[i]) * job.pitch;
 #pragma unroll
@@ -340,10 +347,10 @@ hipError_t launch_line_fft(int M, float2* F, int nlines, int pitch, bool inverse
 }
 
 hipError_t launch_fwd_cols(const FwdColArgs& a, hipStream_t s) {
-  FwdColJob job{a.F, a.psic, a.col_ptr, a.col_planes, a.col_hull, a.N / 2 + 1, a.nimg, a.pitch, a.win,
-                a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
+  FwdColJob job{a.F, a.psic, a.col_ptr, a.col_planes, a.col_hull, a.N / 2 + 1, a.nimg, std::max(a.nparts, 1),
+                a.pitch, a.win, a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
   if (job.nimg == 0) return hipSuccess;
-  const long long total = (long long)job.H * job.nimg;
+  const long long total = (long long)job.H * job.nimg * job.nparts;
   switch (a.M) {
 #define CASE(n)                                                                                   \
   case n:                                                                                         \

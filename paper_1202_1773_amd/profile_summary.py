@@ -4,6 +4,13 @@ Kernel trace (rocpd SQLite database), per kernel and launch shape:
 
     python -m paper_1202_1773_amd.profile_summary <run_results.db>
 
+Vector-ALU instructions from a counter run with SQ_INSTS_VALU (CSV output),
+per labelled kernel shape, with the time they take at full issue rate (a
+wave64 FP32 instruction occupies a 16-lane SIMD for 4 cycles; 4 SIMDs per
+compute unit, 256 compute units at 2.4 GHz; packed FP32 is not used):
+
+    python -m paper_1202_1773_amd.profile_summary --valu <dir> --label ...
+
 HBM traffic from two counter-collection runs (one with FETCH_SIZE, one with
 WRITE_SIZE; CSV output). Both counters are scaled by what they read for the
 largest plain device copy in the same runs (the benchmark's calibration copy
@@ -111,15 +118,36 @@ def traffic(fetch_dir, write_dir, copy_mib, workload, labels, sha):
     return "\n".join(lines)
 
 
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second, whole device
+
+
+def valu(run_dir, labels):
+    counts = read_counters(run_dir, "SQ_INSTS_VALU")
+    lines = ["| kernel | compiled kernel | blocks | launches | SQ_INSTS_VALU / launch | VALU issue us / launch |",
+             "|---|---|---|---|---|---|"]
+    for label in labels:
+        api, rest = label.split("=", 1)
+        kname, blocks = rest.rsplit("@", 1)
+        vals = [v for (n, b), vv in counts.items() if short_name(n) == kname and b == int(blocks) for v in vv]
+        if not vals:
+            raise RuntimeError(f"no dispatch of {kname} with {blocks} blocks")
+        avg = sum(vals) / len(vals)
+        lines.append(f"| {api} | {kname} | {blocks} | {len(vals)} | {avg:.4g} | {avg / VALU_ISSUE_PER_S * 1e6:.1f} |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
     ap.add_argument("--pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--valu", metavar="DIR")
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--workload", type=int, nargs=4, metavar=("M", "N", "J", "B"))
     ap.add_argument("--label", action="append", default=[])
     args = ap.parse_args()
-    if args.pmc:
+    if args.valu:
+        print(valu(args.valu, args.label))
+    elif args.pmc:
         from .build import source_sha
         print(traffic(args.pmc[0], args.pmc[1], args.copy_mib, args.workload, args.label, source_sha()))
     else:
