@@ -58,13 +58,40 @@ NOT_KERNEL_SOURCES = ("batch.hip",)
 def source_sha():
     """Short hash of the sources the kernels and their launch settings come
     from (csrc/*.hip and csrc/*.hpp but the uneven-batch driver), to tie
-    measurements to the code they were taken on."""
+    measurements to the code they were taken on. Comments and blank lines
+    are left out, so that editing a comment keeps a measurement valid."""
     h = hashlib.sha256()
     files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")) and f not in NOT_KERNEL_SOURCES)
     for name in files:
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode() + b"\0" + fh.read())
+        with open(os.path.join(CSRC, name)) as fh:
+            code = _strip_comments(fh.read())
+        h.update(name.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
+
+
+def _strip_comments(text):
+    """C++ source without // and /* */ comments and without blank lines
+    (string and character literals are kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        ch = text[i]
+        if ch in "\"'":
+            j = i + 1
+            while j < n and text[j] != ch:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(ch)
+            i += 1
+    lines = (line.rstrip() for line in "".join(out).split("\n"))
+    return "\n".join(line for line in lines if line)
 
 
 def build_id():

@@ -1,8 +1,10 @@
 // transform_cols.hip -- the column-direction passes of the FFST hot path on
-// gfx950: in-place line FFTs of the half-plane image spectra (k_line_fft),
-// the forward multiply + inverse column FFT per spectrum (k_fwd_lines) and
-// the adjoint's column FFT + multiply + sum over spectra (k_adj_lines). The
-// layouts and the order of the passes are described with the row kernels.
+// gfx950: in-place line FFTs of half-plane spectra (k_line_fft), the
+// forward column pass (k_fwd_cols: per column, the image's column FFT, then
+// the multiply + inverse column FFT for every spectrum that reaches the
+// column) and the adjoint's column FFT + multiply + sum over spectra
+// (k_adj_lines). The layouts and the order of the passes are described with
+// the row kernels.
 #include "fft_core.hpp"
 #include "internal.hpp"
 #include "launch_cfg.hpp"

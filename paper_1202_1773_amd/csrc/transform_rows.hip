@@ -5,18 +5,21 @@
 // Layouts. Every half-plane spectrum (columns c = 0 .. N/2 of a DFT) is kept
 // column-contiguous, [c][r]: the image spectrum F, the adjoint's sum A, the
 // spectra Psi_i, and the per-spectrum intermediates Y_i / Z_i, which only
-// hold the columns [lo_i, lo_i + w_i) where Psi_i is nonzero. The column-
+// hold the columns [lo_i, lo_i + w_i) where Psi_i is nonzero. The column
+// passes read each line of Psi_i only over its shortest cyclic range of
+// nonzero rows (the hull), stored compactly at plan creation. The column-
 // direction FFTs then stream contiguous lines, and the row kernels move
 // between the two layouts through LDS, writing and reading 16 consecutive
 // rows of a column at a time (128-byte segments).
 //
 // Forward (eq. shearletTransform): k_r2c_rows turns the image rows into F
-// (real-to-complex along rows, transposed store); k_line_fft transforms F
-// along the columns; k_fwd_lines multiplies each column line of F by the
-// matching line of Psi_i / (M N), runs the inverse FFT along the column and
-// stores Y_i; k_c2r_rows reads Y_i back by row blocks and finishes every row
-// with a complex-to-real inverse FFT, writing the coefficients. Psi_i * F is
-// never stored.
+// (real-to-complex along rows, transposed store); k_fwd_cols takes one
+// column of F per unit, completes its 2-D FFT with the column FFT in
+// registers, and for every spectrum whose window holds the column multiplies
+// by that line of Psi_i / (M N), runs the inverse FFT along the column and
+// stores the line of Y_i; k_c2r_rows reads Y_i back by row blocks and
+// finishes every row with a complex-to-real inverse FFT, writing the
+// coefficients. Neither fft2(f) nor Psi_i * F is stored.
 //
 // Adjoint / inverse (eq. inverseShearletTransform): k_r2c_rows on the
 // coefficient rows, storing only the window columns (Z_i); k_adj_lines runs,
