@@ -321,7 +321,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-batch and complex-shearlet measurements")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch settings only")
-    ap.add_argument("--tuning", default=None, metavar="NPARTS,BLOCKS_PER_CU,COL_VALUES,ROW_BLOCK",
+    ap.add_argument("--tuning", default=None, metavar="NPARTS,BLOCKS_PER_CU,COL_VALUES,ROW_BLOCK[,FWD_NPARTS]",
                     help="use these launch settings for the batched and plain plans instead of autotuning "
                          "(ffst_tuning in include/ffst.h; for profiling runs that must not sweep)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

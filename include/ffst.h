@@ -238,15 +238,13 @@ int ffst_inverse_complex(const ffst_plan* plan, const float* coeffs, float* f, i
  * Launch tuning of a plan (runtime knobs only; no setting changes what is
  * computed beyond the order of the adjoint's floating-point sums):
  *   nparts        number of lines the spectra of one column (of one image) are
- *                 spread over in the column passes (1 .. 8; 0 = chosen from
- *                 the batch): in the forward every line repeats the column's
- *                 FFT of the image spectrum and runs every nparts-th spectrum,
- *                 in the adjoint every line forms a partial sum, and the
+ *                 spread over in the adjoint's column pass (1 .. 8; 0 = chosen
+ *                 from the batch): every line forms a partial sum, and the
  *                 partial sums are added in a fixed order
  *   blocks_per_cu persistent workgroups per compute unit of every kernel
  *                 (1 .. 32; 0 = each kernel's default)
  * The workspace size depends on nparts: query ffst_workspace_size after
- * changing it.
+ * changing it. ffst_set_tuning keeps the other settings of ffst_tuning.
  */
 int ffst_set_tuning(ffst_plan* plan, int nparts, int blocks_per_cu);
 int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
@@ -265,6 +263,11 @@ int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
  *               up to 512 points (4 .. 16 lanes per row) and half of it for
  *               longer rows (row lengths 64 .. 4096 that are powers of two or
  *               3 * 2^k)
+ *   fwd_nparts  number of lines the spectra of one column (of one image) are
+ *               spread over in the forward's column pass (1 .. 8; 0 = chosen
+ *               from the batch): every line repeats the column's FFT of the
+ *               image spectrum and runs every fwd_nparts-th spectrum of the
+ *               column; the results do not depend on it
  * Other values are rejected with FFST_EINVAL. Every setting computes the same
  * transform; only the rounding order of the FFT stages and of the adjoint's
  * sums differs.
@@ -274,6 +277,7 @@ typedef struct {
     int blocks_per_cu;
     int col_values;
     int row_block;
+    int fwd_nparts;
 } ffst_tuning;
 int ffst_set_tuning_ex(ffst_plan* plan, const ffst_tuning* tuning);
 int ffst_get_tuning_ex(const ffst_plan* plan, ffst_tuning* tuning);
@@ -283,7 +287,8 @@ int ffst_get_tuning_ex(const ffst_plan* plan, ffst_tuning* tuning);
  * setting nparts in {1, 2, 4, 8} x blocks_per_cu in {0, 1, 2, 4, 8, 16} x the
  * compiled col_values x row_block forms (ffst_tuning) whose
  * workspace fits in ws_size bytes (the best of 3 runs after one warm-up, HIP
- * events on `stream`), and keeps the fastest in the plan. coeffs (the
+ * events on `stream`), keeps the fastest, then times the forward alone for
+ * fwd_nparts in {1, 2, 4, 8} with it and keeps the fastest of those. coeffs (the
  * coefficient buffer for the plan's kind, as for the transform calls) and
  * out ([batch][M][N]) are scratch. Synchronous. *best_ms (may be NULL)
  * receives the fastest time of one forward + adjoint. The tuning calls change

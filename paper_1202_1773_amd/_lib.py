@@ -51,7 +51,7 @@ class FfstError(RuntimeError):
 
 class ffst_tuning(ctypes.Structure):
     _fields_ = [("nparts", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("col_values", ctypes.c_int),
-                ("row_block", ctypes.c_int)]
+                ("row_block", ctypes.c_int), ("fwd_nparts", ctypes.c_int)]
 
 
 class ffst_options(ctypes.Structure):
@@ -255,13 +255,13 @@ def ffst_get_tuning(plan):
     return n.value, b.value
 
 
-def ffst_set_tuning_ex(plan, nparts=0, blocks_per_cu=0, col_values=0, row_block=0):
-    t = ffst_tuning(int(nparts), int(blocks_per_cu), int(col_values), int(row_block))
+def ffst_set_tuning_ex(plan, nparts=0, blocks_per_cu=0, col_values=0, row_block=0, fwd_nparts=0):
+    t = ffst_tuning(int(nparts), int(blocks_per_cu), int(col_values), int(row_block), int(fwd_nparts))
     _check(load().ffst_set_tuning_ex(plan, ctypes.byref(t)), "ffst_set_tuning_ex")
 
 
 def ffst_get_tuning_ex(plan):
-    """dict(nparts, blocks_per_cu, col_values, row_block) of a plan."""
+    """dict(nparts, blocks_per_cu, col_values, row_block, fwd_nparts) of a plan."""
     t = ffst_tuning()
     _check(load().ffst_get_tuning_ex(plan, ctypes.byref(t)), "ffst_get_tuning_ex")
     return {k: getattr(t, k) for k, _ in ffst_tuning._fields_}

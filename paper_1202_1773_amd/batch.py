@@ -123,7 +123,7 @@ class BatchPlan:
         _lib.ffst_batch_tune(self._h, f.data_ptr(), c.data_ptr(), y.data_ptr(), self.workspace(), self._stream())
 
     def class_tuning(self):
-        """Per size class: dict(M, N, J, nparts, blocks_per_cu, col_values, row_block)."""
+        """Per size class: dict(M, N, J, nparts, blocks_per_cu, col_values, row_block, fwd_nparts)."""
         out = []
         for c in range(self.classes):
             h = _lib.ffst_batch_class(self._h, c)[0]

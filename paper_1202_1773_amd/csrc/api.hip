@@ -52,7 +52,8 @@ struct ffst_plan {
   std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
   std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
   long long chunk_elems = 0;    // target size of one unit's compact buffer
-  int tune_nparts = 0;          // lines per column in the column passes (0: heuristic)
+  int tune_nparts = 0;          // lines per column in the adjoint column pass (0: heuristic)
+  int tune_fwd_nparts = 0;      // lines per column in the forward column pass (0: heuristic)
   int tune_blocks_per_cu = 0;   // persistent blocks per CU (0: per-kernel default)
   int tune_col_values = 0;      // values per lane of the column-line FFTs (0: default)
   int tune_row_block = 0;       // row blocks of the row kernels (0/1: default height, 2: the alternative)
@@ -269,7 +270,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // adjoint's sum over spectra is spread over blocks.
 struct Schedule {
   int chunk_imgs = 1;     // images per unit
-  int nparts = 1;         // lines per (image, column) in the column passes (adjoint: partial sums)
+  int nparts = 1;         // lines per (image, column) in the adjoint column pass (partial sums)
+  int fwd_nparts = 1;     // lines per (image, column) in the forward column pass
   bool fused = true;      // adjoint column pass ends with its inverse FFT
   size_t fa_bytes = 0, yz_bytes = 0, part_bytes = 0;
 };
@@ -296,6 +298,11 @@ Schedule schedule(const ffst_plan* p, int batch) {
   sc.nparts = (int)std::min<long long>(8, std::max<long long>(1, (want + units - 1) / units));
   if (p->tune_nparts > 0) sc.nparts = p->tune_nparts;
   sc.fused = (ngroups == 1 && sc.nparts == 1);
+  // forward column lines: every line repeats the column's FFT of the image
+  // spectrum, no partial sums, so it is split further (~8 lines per SIMD)
+  const long long want_fwd = 32LL * 256;
+  sc.fwd_nparts = (int)std::min<long long>(8, std::max<long long>(1, (want_fwd + units - 1) / units));
+  if (p->tune_fwd_nparts > 0) sc.fwd_nparts = p->tune_fwd_nparts;
   sc.fa_bytes = align256((size_t)batch * p->pitch * p->H * sizeof(float2));
   sc.yz_bytes = align256((size_t)sc.chunk_imgs * (size_t)max_group * sizeof(float2));
   sc.part_bytes = sc.fused ? 0 : align256((size_t)sc.nparts * sc.chunk_imgs * p->pitch * p->H * sizeof(float2));
@@ -849,7 +856,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
       FwdColArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_col_ptr + g * (p->H + 1), p->d_col_planes,
-                    p->d_col_hull, nimg, sc.nparts, p->pitch, plane_windows(p), unit_stride, base, Y, scale,
+                    p->d_col_hull, nimg, sc.fwd_nparts, p->pitch, plane_windows(p), unit_stride, base, Y, scale,
                     p->twM};
       e = timed(KID_FWD_COLS, s, [&] { return launch_fwd_cols(fa, s); });
       if (e != hipSuccess) break;
@@ -1045,7 +1052,7 @@ int ffst_inverse_complex(const ffst_plan* p, const float* coeffs, float* f, int 
 
 int ffst_set_tuning(ffst_plan* p, int nparts, int blocks_per_cu) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
-  ffst_tuning t{nparts, blocks_per_cu, p->tune_col_values, p->tune_row_block};
+  ffst_tuning t{nparts, blocks_per_cu, p->tune_col_values, p->tune_row_block, p->tune_fwd_nparts};
   return ffst_set_tuning_ex(p, &t);
 }
 
@@ -1060,6 +1067,8 @@ int ffst_set_tuning_ex(ffst_plan* p, const ffst_tuning* t) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (!t) return fail(FFST_EINVAL, "tuning must be non-NULL");
   if (t->nparts < 0 || t->nparts > 8) return fail(FFST_EINVAL, "nparts must be in [0, 8] (got %d)", t->nparts);
+  if (t->fwd_nparts < 0 || t->fwd_nparts > 8)
+    return fail(FFST_EINVAL, "fwd_nparts must be in [0, 8] (got %d)", t->fwd_nparts);
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
     return fail(FFST_EINVAL, "blocks_per_cu must be in [0, 32] (got %d)", t->blocks_per_cu);
   const int alt = alt_col_values_of(p);
@@ -1069,6 +1078,7 @@ int ffst_set_tuning_ex(ffst_plan* p, const ffst_tuning* t) {
   if (t->row_block < 0 || t->row_block > 2 || (t->row_block == 2 && !row_block_tunable_of(p)))
     return fail(FFST_EINVAL, "row_block %d is not available for row length %d", t->row_block, p->N);
   p->tune_nparts = t->nparts;
+  p->tune_fwd_nparts = t->fwd_nparts;
   p->tune_blocks_per_cu = t->blocks_per_cu;
   p->tune_col_values = t->col_values == col_values(p->M) ? 0 : t->col_values;
   p->tune_row_block = t->row_block == 2 ? 2 : 0;
@@ -1079,6 +1089,7 @@ int ffst_get_tuning_ex(const ffst_plan* p, ffst_tuning* t) {
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (!t) return fail(FFST_EINVAL, "tuning must be non-NULL");
   t->nparts = p->tune_nparts;
+  t->fwd_nparts = p->tune_fwd_nparts;
   t->blocks_per_cu = p->tune_blocks_per_cu;
   t->col_values = p->tune_col_values ? p->tune_col_values : col_values(p->M);
   t->row_block = p->tune_row_block == 2 ? 2 : 1;
@@ -1107,54 +1118,79 @@ int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch
   const int ncolv = alt ? 2 : 1, nrows = row_block_tunable_of(p) ? 2 : 1;
   ffst_tuning saved{};
   saved.nparts = p->tune_nparts;
+  saved.fwd_nparts = p->tune_fwd_nparts;
   saved.blocks_per_cu = p->tune_blocks_per_cu;
   saved.col_values = p->tune_col_values;
   saved.row_block = p->tune_row_block;
+  auto apply = [p](const ffst_tuning& t) {
+    p->tune_nparts = t.nparts;
+    p->tune_fwd_nparts = t.fwd_nparts;
+    p->tune_blocks_per_cu = t.blocks_per_cu;
+    p->tune_col_values = t.col_values;
+    p->tune_row_block = t.row_block;
+  };
+  int st = FFST_OK;
+  // best of 3 runs after one warm-up of forward (+ adjoint), in ms
+  auto time_it = [&](bool with_adjoint) {
+    double t_min = -1.0;
+    for (int rep = 0; rep < 4 && st == FFST_OK; ++rep) {
+      (void)hipEventRecord(a, s);
+      st = fwd(p, f, coeffs, batch, ws, stream);
+      if (st == FFST_OK && with_adjoint) st = adj(p, coeffs, out, batch, ws, stream);
+      (void)hipEventRecord(b, s);
+      float ms = 0.f;
+      if (st == FFST_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+        st = fail(FFST_EDEVICE, "ffst_tune: event timing failed");
+      if (st == FFST_OK && rep > 0 && (t_min < 0 || ms < t_min)) t_min = ms;
+    }
+    return t_min;
+  };
+  // Shapes shared by both directions and the adjoint's split, timed on
+  // forward + adjoint with the forward split as it was set; then the
+  // forward's own split, timed on the forward alone (it changes nothing else).
   double best = -1.0;
   ffst_tuning best_t = saved;
-  int st = FFST_OK;
   for (int iv = 0; iv < ncolv && st == FFST_OK; ++iv)
     for (int ir = 0; ir < nrows && st == FFST_OK; ++ir)
       for (int n : parts) {
         for (int bc : per_cu) {
-          p->tune_nparts = n;
-          p->tune_blocks_per_cu = bc;
-          p->tune_col_values = colv[iv];
-          p->tune_row_block = rows[ir];
+          const ffst_tuning cand{n, bc, colv[iv], rows[ir], saved.fwd_nparts};
+          apply(cand);
           if (ws_bytes(p, batch) > ws_size) continue;
-          double t_min = -1.0;
-          for (int rep = 0; rep < 4 && st == FFST_OK; ++rep) {  // first run is a warm-up
-            (void)hipEventRecord(a, s);
-            st = fwd(p, f, coeffs, batch, ws, stream);
-            if (st == FFST_OK) st = adj(p, coeffs, out, batch, ws, stream);
-            (void)hipEventRecord(b, s);
-            float ms = 0.f;
-            if (st == FFST_OK &&
-                (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
-              st = fail(FFST_EDEVICE, "ffst_tune: event timing failed");
-            if (st == FFST_OK && rep > 0 && (t_min < 0 || ms < t_min)) t_min = ms;
-          }
+          const double t = time_it(true);
           if (st != FFST_OK) break;
-          if (best < 0 || t_min < best) {
-            best = t_min;
-            best_t = ffst_tuning{n, bc, colv[iv], rows[ir]};
+          if (best < 0 || t < best) {
+            best = t;
+            best_t = cand;
           }
         }
         if (st != FFST_OK) break;
       }
+  if (st == FFST_OK && best >= 0) {
+    double best_f = -1.0;
+    int best_fn = best_t.fwd_nparts;
+    for (int fn : parts) {
+      ffst_tuning cand = best_t;
+      cand.fwd_nparts = fn;
+      apply(cand);
+      const double t = time_it(false);
+      if (st != FFST_OK) break;
+      if (best_f < 0 || t < best_f) {
+        best_f = t;
+        best_fn = fn;
+      }
+    }
+    best_t.fwd_nparts = best_fn;
+    apply(best_t);
+    if (st == FFST_OK) best = time_it(true);
+  }
   release_event(a);
   release_event(b);
   if (st != FFST_OK || best < 0) {
-    p->tune_nparts = saved.nparts;
-    p->tune_blocks_per_cu = saved.blocks_per_cu;
-    p->tune_col_values = saved.col_values;
-    p->tune_row_block = saved.row_block;
+    apply(saved);
     return st != FFST_OK ? st : fail(FFST_EINVAL, "ffst_tune: workspace too small for every candidate");
   }
-  p->tune_nparts = best_t.nparts;
-  p->tune_blocks_per_cu = best_t.blocks_per_cu;
-  p->tune_col_values = best_t.col_values;
-  p->tune_row_block = best_t.row_block;
+  apply(best_t);
   if (best_ms) *best_ms = best;
   return ok();
 }

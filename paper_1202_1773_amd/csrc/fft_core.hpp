@@ -340,6 +340,63 @@ struct TwiddleRegs {
     __asm__ __volatile__("" : "+v"(j));
     load_stage<1>(j, table, ts);
   }
+  // Multiplies a[1 .. R-1] of butterfly m of stage S by their twiddles.
+  template <int S, int R, bool INV>
+  __device__ __forceinline__ void apply(float2 (&a)[R], int m) const {
+    constexpr int OFF = P::tw_offset(S);
+#pragma unroll
+    for (int t = 1; t < R; ++t) {
+      const float2 x = w[OFF + m * (R - 1) + t - 1];
+      a[t] = INV ? cmulc(a[t], x) : cmul(a[t], x);
+    }
+  }
+};
+
+// The same twiddles with one register pair per butterfly instead of R - 1:
+// only w = table[k * TSTEP] is kept, and w^t (t = 2 .. R-1) is rebuilt at
+// every use by squaring and one more product (w^2t = (w^t)^2,
+// w^(2t+1) = w^2t * w), at most 2 log2(R) roundings away from the table
+// value. The seed passes through an empty asm at each use, so the compiler
+// cannot hoist the powers out of the caller's loops back into registers.
+// For kernels whose occupancy is set by their registers and whose vector ALU
+// has time to spare.
+template <int L, int V>
+struct TwiddleSeeds {
+  using P = RadixPlan<L, V>;
+  static constexpr int seed_offset(int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += V / P::radix(i);
+    return o;
+  }
+  static constexpr int NSEED = seed_offset(P::stages());
+  float2 w[NSEED > 0 ? NSEED : 1];
+
+  template <int S>
+  __device__ __forceinline__ void load_stage(int j, const float2* __restrict__ table, int ts) {
+    if constexpr (S < P::stages()) {
+      constexpr int R = P::radix(S), SP = P::span(S), NB = V / R, TSTEP = L / (SP * R);
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        const int k = (j + m * P::G) % SP;
+        w[seed_offset(S) + m] = table[(k * TSTEP) * ts];
+      }
+      load_stage<S + 1>(j, table, ts);
+    }
+  }
+  __device__ __forceinline__ void load(int j, const float2* __restrict__ table, int ts) {
+    __asm__ __volatile__("" : "+v"(j));
+    load_stage<1>(j, table, ts);
+  }
+  template <int S, int R, bool INV>
+  __device__ __forceinline__ void apply(float2 (&a)[R], int m) const {
+    float2 p[R];
+    p[1] = w[seed_offset(S) + m];
+    __asm__ __volatile__("" : "+v"(p[1].x), "+v"(p[1].y));
+#pragma unroll
+    for (int t = 2; t < R; ++t) p[t] = (t % 2 == 0) ? cmul(p[t / 2], p[t / 2]) : cmul(p[t - 1], p[1]);
+#pragma unroll
+    for (int t = 1; t < R; ++t) a[t] = INV ? cmulc(a[t], p[t]) : cmul(a[t], p[t]);
+  }
 };
 
 enum SyncKind { kWave = 0, kBlock = 1 };
@@ -362,23 +419,17 @@ __device__ __forceinline__ int lpad(int i) {
   return i + i / V;
 }
 
-template <int L, int V, int S, bool INV, int SYNC>
-__device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* lds, const TwiddleRegs<L, V>& tw) {
+template <int L, int V, int S, bool INV, int SYNC, class TW>
+__device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* lds, const TW& tw) {
   using P = RadixPlan<L, V>;
-  constexpr int G = P::G, R = P::radix(S), SP = P::span(S), NB = V / R, OFF = P::tw_offset(S);
+  constexpr int G = P::G, R = P::radix(S), SP = P::span(S), NB = V / R;
   constexpr bool LAST = (S + 1 == P::stages());
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
     float2 a[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) a[t] = u[m + t * NB];
-    if constexpr (S > 0) {
-#pragma unroll
-      for (int t = 1; t < R; ++t) {
-        const float2 w = tw.w[OFF + m * (R - 1) + t - 1];
-        a[t] = INV ? cmulc(a[t], w) : cmul(a[t], w);
-      }
-    }
+    if constexpr (S > 0) tw.template apply<S, R, INV>(a, m);
     Dft<R, INV>::run(a);
     if constexpr (LAST) {
 #pragma unroll
@@ -400,9 +451,10 @@ __device__ __forceinline__ void stockham_stage(float2 (&u)[V], int j, float2* ld
 }
 
 // In-place length-L FFT of the group's values (forward: kernel exp(-2 pi i nk/L),
-// inverse: exp(+2 pi i nk/L), both unnormalised).
-template <int L, int V, bool INV, int SYNC>
-__device__ __forceinline__ void fft_group(float2 (&u)[V], int j, float2* lds, const TwiddleRegs<L, V>& tw) {
+// inverse: exp(+2 pi i nk/L), both unnormalised). TW is TwiddleRegs<L, V> or
+// TwiddleSeeds<L, V>.
+template <int L, int V, bool INV, int SYNC, class TW>
+__device__ __forceinline__ void fft_group(float2 (&u)[V], int j, float2* lds, const TW& tw) {
   stockham_stage<L, V, 0, INV, SYNC>(u, j, lds, tw);
 }
 

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__((LineCfg<M, VV>::THREADS)) k_fwd_cols(FwdColJo
   const int g = group_index<C>();
   const int j = group_lane<C>();
   float2* my = lds + g * C::STRIDE;
-  TwiddleRegs<M, V> tw;
+  TwiddleSeeds<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.H * job.nimg * job.nparts;
   for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
@@ -181,7 +181,7 @@ __device__ __forceinline__ void adj_lines_body(const AdjLineJob& job) {
   const int g = group_index<C>();
   const int j = group_lane<C>();
   float2* my = lds + g * C::STRIDE;
-  TwiddleRegs<M, V> tw;
+  TwiddleSeeds<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.H * job.nimg * job.nparts;
   for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {

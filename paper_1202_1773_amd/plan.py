@@ -120,13 +120,13 @@ class Plan:
         """(nparts, blocks_per_cu) of the plan; 0 means the built-in choice."""
         return _lib.ffst_get_tuning(self._h)
 
-    def set_tuning(self, nparts=0, blocks_per_cu=0, col_values=0, row_block=0):
+    def set_tuning(self, nparts=0, blocks_per_cu=0, col_values=0, row_block=0, fwd_nparts=0):
         """Launch settings (ffst_tuning in include/ffst.h); 0 keeps a default."""
-        _lib.ffst_set_tuning_ex(self._h, nparts, blocks_per_cu, col_values, row_block)
+        _lib.ffst_set_tuning_ex(self._h, nparts, blocks_per_cu, col_values, row_block, fwd_nparts)
         self._ws.clear()
 
     def tuning_ex(self):
-        """All launch settings: dict(nparts, blocks_per_cu, col_values, row_block)."""
+        """All launch settings: dict(nparts, blocks_per_cu, col_values, row_block, fwd_nparts)."""
         return _lib.ffst_get_tuning_ex(self._h)
 
     def tune(self, x):

@@ -168,17 +168,17 @@ def test_autotuner():
     t = plan.tuning_ex()
     log(f"  best {best:.4f} ms at {t}")
     assert best > 0 and 1 <= t["nparts"] <= 8 and t["blocks_per_cu"] in (0, 1, 2, 4, 8, 16)
-    assert t["col_values"] in (8, 16) and t["row_block"] in (1, 2)
+    assert t["col_values"] in (8, 16) and t["row_block"] in (1, 2) and 1 <= t["fwd_nparts"] <= 8
     c1 = plan.forward(x)
-    # the forward does not depend on nparts, blocks per CU or the row block
-    # height; another column lane width only changes the rounding order
+    # the forward does not depend on the splits, blocks per CU or the row
+    # block height; another column lane width only changes the rounding order
     if t["col_values"] == 8:
         assert torch.equal(c0, c1)
     assert rel_l2(c1.cpu().numpy(), c0.cpu().numpy()) <= 1e-6
     assert rel_l2(plan.adjoint(c1).cpu().numpy(), x.cpu().numpy()) <= TOL
     plan.set_tuning(0, 0)
     assert plan.tuning() == (0, 0)
-    assert plan.tuning_ex() == {"nparts": 0, "blocks_per_cu": 0, "col_values": 8, "row_block": 1}
+    assert plan.tuning_ex() == {"nparts": 0, "blocks_per_cu": 0, "col_values": 8, "row_block": 1, "fwd_nparts": 0}
     plan.close()
     imgs = small_images()
     bp = BatchPlan(SMALL, SMALL_J)
@@ -188,8 +188,10 @@ def test_autotuner():
     # faster with them; otherwise every class is back at the defaults
     tuned = bp.class_tuning()
     log(f"  batch class settings {tuned}")
-    defaults = all(t["nparts"] == 0 and t["blocks_per_cu"] == 0 and t["row_block"] == 1 for t in tuned)
-    assert defaults or all(1 <= t["nparts"] <= 8 and t["blocks_per_cu"] in (0, 1, 2, 4, 8, 16) for t in tuned)
+    defaults = all(t["nparts"] == 0 and t["blocks_per_cu"] == 0 and t["row_block"] == 1 and t["fwd_nparts"] == 0
+                   for t in tuned)
+    assert defaults or all(1 <= t["nparts"] <= 8 and t["blocks_per_cu"] in (0, 1, 2, 4, 8, 16)
+                           and 1 <= t["fwd_nparts"] <= 8 for t in tuned)
     y = bp.adjoint(bp.forward(f))
     for b, img in enumerate(bp.images(y)):
         assert rel_l2(img.cpu().numpy(), imgs[b]) <= TOL

@@ -2,6 +2,7 @@
 warnings as errors, links against libffst.so and, on the CPU, gets the
 documented errors back from calls on NULL handles and bad arguments."""
 
+import ctypes
 import os
 import shutil
 import subprocess
@@ -62,3 +63,41 @@ def test_header_compiles_as_c_and_links(tmp_path):
     run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert run.returncode == 0, (run.stdout, run.stderr)
     assert run.stdout.strip() == "0"
+
+
+LAYOUT_SOURCE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "ffst.h"
+
+int main(void) {
+    printf("ffst_tuning %zu", sizeof(ffst_tuning));
+    printf(" nparts %zu blocks_per_cu %zu col_values %zu row_block %zu fwd_nparts %zu\n",
+           offsetof(ffst_tuning, nparts), offsetof(ffst_tuning, blocks_per_cu), offsetof(ffst_tuning, col_values),
+           offsetof(ffst_tuning, row_block), offsetof(ffst_tuning, fwd_nparts));
+    printf("ffst_options %zu", sizeof(ffst_options));
+    printf(" max_scale_min %zu shearlet %zu complex_shearlets %zu aux_order %zu\n",
+           offsetof(ffst_options, max_scale_min), offsetof(ffst_options, shearlet),
+           offsetof(ffst_options, complex_shearlets), offsetof(ffst_options, aux_order));
+    return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    # the ctypes structures of the binding must lay out like the header's
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_SOURCE)
+    exe = tmp_path / "layout"
+    res = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                          str(exe)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60).stdout.split("\n")
+    for line, cls in zip(out, (_lib.ffst_tuning, _lib.ffst_options)):
+        words = line.split()
+        assert words[0] == cls.__name__ and int(words[1]) == ctypes.sizeof(cls), (line, cls)
+        fields = dict(zip(words[2::2], (int(w) for w in words[3::2])))
+        assert fields == {name: getattr(cls, name).offset for name, _ in cls._fields_}, (line, cls)
