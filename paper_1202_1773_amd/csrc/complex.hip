@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_inv(CRowJob jo
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
   float2* zr = lds + tr * C::STRIDE;
-  TwiddleRegs<L, V> tw;
+  TwiddleSeeds<L, V> tw;
   tw.load(j, job.twN, 1);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
   const float2* zr = lds + tr * C::STRIDE;
-  TwiddleRegs<L, V> tw;
+  TwiddleSeeds<L, V> tw;
   tw.load(j, job.twN, 1);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
   const int j = group_lane<C>();
-  TwiddleRegs<M, V> tw;
+  TwiddleSeeds<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.nlines * job.nimg;
   float2 fn[V];
@@ -251,7 +251,7 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
   const int g = group_index<C>();
   const int j = group_lane<C>();
   float2* my = lds + g * C::STRIDE;
-  TwiddleRegs<M, V> tw;
+  TwiddleSeeds<M, V> tw;
   tw.load(j, job.twM, 1);
   const int total = job.H * job.nimg * job.nparts;
   for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {

@@ -89,7 +89,7 @@ __device__ __forceinline__ void r2c_rows_body(const RowJob& job) {
   const int cstep = NT / rb;
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
-  TwiddleRegs<L, V> tw;
+  TwiddleSeeds<L, V> tw;
   tw.load(j, job.twN, 2);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__((RowCfg<L, RBM>::THREADS)) k_c2r_rows(RowJob j
   const int tr = threadIdx.x % rb;
   const int tc = (!SMALL || threadIdx.x < rb * (NT / rb)) ? threadIdx.x / rb : (1 << 29);
   float2* my = lds + g * C::STRIDE;
-  TwiddleRegs<L, V> tw;
+  TwiddleSeeds<L, V> tw;
   tw.load(j, job.twN, 2);
   for (int k = threadIdx.x; k < L; k += NT) wsh[k] = job.twN[k];
   const int bpp = job.M / rb;
@@ -274,7 +274,7 @@ __device__ __forceinline__ void r2c_rows_odd_body(const RowJob& job) {
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
   const float2* zr = lds + tr * C::STRIDE;
-  TwiddleRegs<N, V> tw;
+  TwiddleSeeds<N, V> tw;
   tw.load(j, job.twN, 1);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(CRowCfg<N>::THREADS) k_c2r_rows_odd(RowJob job
   const bool row_ok = g < rb;
   float2* my = lds + g * C::STRIDE;
   float2* zr = lds + tr * C::STRIDE;
-  TwiddleRegs<N, V> tw;
+  TwiddleSeeds<N, V> tw;
   tw.load(j, job.twN, 1);
   const int bpp = job.M / rb;
   const int nunits = job.nimg * job.nplanes * bpp;

@@ -58,6 +58,9 @@ def test_zero_spectra(M, N, J):
     cplan.close()
 
 
+# The FP64 oracle's textbook FFTs of a 4096 x 4096 image take about two
+# minutes of host time, more than the per-test limit of the GPU runs.
+@pytest.mark.timeout(400)
 @pytest.mark.parametrize("M,N,J,planes", [(4096, 4096, 6, [0, 252]), (3072, 3072, 5, [3, 124]),
                                           (1536, 1536, 5, [0, 11, 50, 124])])
 def test_largest_sides_sampled(M, N, J, planes):
