@@ -367,6 +367,21 @@ const char* ffst_build_id(void);
 size_t ffst_device_bytes(void);
 
 /*
+ * Tracing (no calls; read from the environment once per process):
+ *   FFST_LOG=1          plan and batch creation (sizes, windows, hull values,
+ *                       device bytes), tuning changes and tuner results,
+ *                       destruction, and every error with its status and
+ *                       message, one line each on stderr
+ *   FFST_LOG=2          also every transform call with its schedule (images
+ *                       per unit, lines per column, adjoint form)
+ *   FFST_LOG=<l>:<path> level <l> appended to the file <path>; a bare path
+ *                       means level 1 into that file; unset, empty or 0: off
+ * Independently, every C ABI call and every kernel launch opens a roctx
+ * range named after it (ffst_forward, k_fwd_cols, ...), which rocprofv3
+ * --marker-trace shows on its timeline.
+ */
+
+/*
  * Kernel timing. With profiling enabled, every launch of a kernel whose id
  * bit is set in `mask` is bracketed by two HIP events recorded on the
  * launch's own stream. ffst_profile_read synchronises on the recorded

@@ -26,7 +26,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffst.so")
 LIB_ASAN = os.path.join(HERE, "libffst_asan.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ffst.h")
-SOURCES = ["spectra.hip", "transform_rows.hip", "transform_cols.hip", "complex.hip", "api.hip", "batch.hip"]
+SOURCES = ["spectra.hip", "transform_rows.hip", "transform_cols.hip", "complex.hip", "api.hip", "batch.hip",
+           "trace.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -34,6 +35,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 NOISE = "packed-fp32-ops"
+LIBS = ["-lrocprofiler-sdk-roctx"]   # roctx ranges (trace.hip)
 SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
 SANITIZE_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
@@ -51,8 +53,9 @@ def asan_runtime():
 
 
 # Host code that launches no kernel of a single-size plan: the uneven-batch
-# driver (it replays the plans' own launches in a graph).
-NOT_KERNEL_SOURCES = ("batch.hip",)
+# driver (it replays the plans' own launches in a graph) and the log / roctx
+# tracing.
+NOT_KERNEL_SOURCES = ("batch.hip", "trace.hip")
 
 
 def source_sha():
@@ -137,7 +140,7 @@ def build(verbose=False, sanitize=False):
                 print(err, file=sys.stderr)
         tmp = out_lib + ".tmp"
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *(SANITIZE_LINK if sanitize else []), *objs,
-                "-o", tmp]
+                *LIBS, "-o", tmp]
         rc, err = _run(link)
         if rc != 0:
             raise RuntimeError("link failed:\n" + err)

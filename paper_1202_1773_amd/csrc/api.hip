@@ -71,6 +71,7 @@ int ffst::fail(int status, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+  logf(1, "error %d: %s", status, buf);
   return status;
 }
 
@@ -169,9 +170,12 @@ hipEvent_t pooled_event() {
 
 // Set for the duration of a call that must not create HIP objects (events).
 thread_local bool t_no_timing = false;
+// Set while the autotuner runs its candidates (their calls are not logged).
+thread_local bool t_tuning_calls = false;
 
 template <class Fn>
 hipError_t timed(int id, hipStream_t s, Fn&& fn) {
+  const Range range(kKernelNames[id]);
   if (t_no_timing || g_profile_suspended.load(std::memory_order_relaxed) ||
       !((g_mask.load(std::memory_order_relaxed) >> id) & 1u))
     return fn();
@@ -561,6 +565,7 @@ extern "C" {
 int ffst_spectra(int M, int N, int J, ffst_plan** out) { return ffst_spectra_ex(M, N, J, nullptr, out); }
 
 int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** out) {
+  const Range range("ffst_spectra_ex");
   const AllocScope alloc_scope;
   if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
   *out = nullptr;
@@ -752,6 +757,17 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
   *out = p;
+  if (log_level() >= 1) {
+    long long wcols = 0;
+    for (int i = 0; i < p->eta; ++i) wcols += p->w[i];
+    logf(1,
+         "plan %p: %d x %d, J = %d, eta = %d, %s %s shearlets, aux order %d, %s finest scale; window columns %lld "
+         "of %lld, spectrum hull values %zu, plane groups %d; device bytes held by the library %zu",
+         (void*)p, M, N, J, p->eta, o.complex_shearlets ? "complex" : "real",
+         o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? "smooth Meyer" : "Meyer", o.aux_order,
+         o.max_scale_min ? "'min'" : "'max'", wcols, (long long)p->eta * (o.complex_shearlets ? p->N : p->H),
+         cplx ? (size_t)0 : psic.size(), ngroups, ffst_device_bytes());
+  }
   return ok();
 }
 
@@ -828,6 +844,7 @@ int ffst_shearlet_index(int J, int kind, int j, int k, int* i) {
 }
 
 int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
+  const Range range("ffst_forward");
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, false, "ffst_forward") != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
@@ -837,6 +854,9 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
+  if (!t_tuning_calls)
+    logf(2, "plan %p ffst_forward: %d image(s), %d per unit, %d line(s) per column", (const void*)p, batch,
+         sc.chunk_imgs, sc.fwd_nparts);
   float2* F = static_cast<float2*>(ws);
   float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
   const long long MH = (long long)p->pitch * p->H;   // one image of F / A
@@ -869,6 +889,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
 }
 
 int ffst_forward_noalloc(const ffst_plan* p, const float* f, float* coeffs, int batch, void* stream) {
+  const Range range("ffst_forward_noalloc");
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, false, "ffst_forward_noalloc") != FFST_OK) return FFST_EINVAL;
   if (batch < 0) return fail(FFST_EINVAL, "batch must be >= 0 (got %d)", batch);
@@ -895,6 +916,7 @@ namespace {
 // read as s * sign(c).
 int adjoint_real(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream,
                  const float* sign_scale, const char* what) {
+  const Range range(what);
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, false, what) != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
@@ -904,6 +926,9 @@ int adjoint_real(const ffst_plan* p, const float* coeffs, float* f, int batch, v
   const TuningScope tuning(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
+  if (!t_tuning_calls)
+    logf(2, "plan %p %s: %d image(s), %d per unit, %d line(s) per column (%s)", (const void*)p, what, batch,
+         sc.chunk_imgs, sc.nparts, sc.fused ? "inverse FFT in the column pass" : "partial sums");
   float2* A = static_cast<float2*>(ws);
   float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
   float2* P = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes + sc.yz_bytes);
@@ -957,6 +982,7 @@ int ffst_inverse(const ffst_plan* p, const float* coeffs, float* f, int batch, v
 }
 
 int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int batch, void* ws, void* stream) {
+  const Range range("ffst_forward_complex");
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, true, "ffst_forward_complex") != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
@@ -999,6 +1025,7 @@ int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int 
 }
 
 int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int batch, void* ws, void* stream) {
+  const Range range("ffst_adjoint_complex");
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
   if (reject_kind(p, true, "ffst_adjoint_complex") != FFST_OK) return FFST_EINVAL;
   const size_t img = (size_t)p->M * p->N * sizeof(float);
@@ -1082,6 +1109,8 @@ int ffst_set_tuning_ex(ffst_plan* p, const ffst_tuning* t) {
   p->tune_blocks_per_cu = t->blocks_per_cu;
   p->tune_col_values = t->col_values == col_values(p->M) ? 0 : t->col_values;
   p->tune_row_block = t->row_block == 2 ? 2 : 0;
+  logf(1, "plan %p tuning: nparts %d, fwd_nparts %d, blocks per CU %d, col_values %d, row_block %d", (void*)p,
+       t->nparts, t->fwd_nparts, t->blocks_per_cu, t->col_values, t->row_block);
   return ok();
 }
 
@@ -1098,7 +1127,13 @@ int ffst_get_tuning_ex(const ffst_plan* p, ffst_tuning* t) {
 
 int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch, void* ws, size_t ws_size,
               void* stream, double* best_ms) {
+  const Range range("ffst_tune");
   if (!plan_ok(p)) return fail(FFST_EBADPLAN, "invalid plan");
+  struct QuietCalls {
+    bool saved = t_tuning_calls;
+    QuietCalls() { t_tuning_calls = true; }
+    ~QuietCalls() { t_tuning_calls = saved; }
+  } quiet;
   if (batch < 1) return fail(FFST_EINVAL, "batch must be >= 1 (got %d)", batch);
   if (!f || !coeffs || !out || !ws) return fail(FFST_EINVAL, "buffers must be non-NULL");
   const bool cplx = p->opt.complex_shearlets == 1;
@@ -1192,11 +1227,17 @@ int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch
   }
   apply(best_t);
   if (best_ms) *best_ms = best;
+  logf(1,
+       "plan %p tuned for %d image(s): nparts %d, fwd_nparts %d, blocks per CU %d, col_values %d, row_block %d; "
+       "forward + adjoint %.4f ms",
+       (void*)p, batch, best_t.nparts, best_t.fwd_nparts, best_t.blocks_per_cu,
+       best_t.col_values ? best_t.col_values : col_values(p->M), best_t.row_block == 2 ? 2 : 1, best);
   return ok();
 }
 
 void ffst_destroy(ffst_plan* p) {
   if (!plan_ok(p)) return;
+  logf(1, "plan %p destroyed", (void*)p);
   (void)hipDeviceSynchronize();
   free_plan(p);
 }

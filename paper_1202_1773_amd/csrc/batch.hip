@@ -147,6 +147,7 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 int run(ffst_batch* b, int dir, const float* in, float* out, void* ws, void* stream, const char* what) {
+  const Range range(what);
   if (!batch_ok(b)) return fail(FFST_EBADPLAN, "%s: invalid batch", what);
   if (!in || !out || !ws) return fail(FFST_EINVAL, "%s: buffers must be non-NULL", what);
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(FFST_EINVAL, "%s: workspace must be 256-byte aligned", what);
@@ -220,6 +221,7 @@ extern "C" {
 
 int ffst_batch_create(int count, const int* M, const int* N, const int* J, const ffst_options* opt,
                       ffst_batch** out) {
+  const Range range("ffst_batch_create");
   const AllocScope alloc_scope;
   if (!out) return fail(FFST_EINVAL, "out must be non-NULL");
   *out = nullptr;
@@ -306,6 +308,14 @@ int ffst_batch_create(int count, const int* M, const int* N, const int* J, const
     return fail(FFST_EDEVICE, "stream/event creation: %s", hipGetErrorString(e));
   }
   *out = b;
+  logf(1, "batch %p: %d image(s) in %zu size class(es), %lld coefficients, workspace %zu bytes", (void*)b, count, nc,
+       (long long)b->coef_total, b->ws_total);
+  for (size_t c = 0; c < nc; ++c) {
+    int cm = 0, cn = 0, cj = 0;
+    (void)ffst_plan_info(b->plans[c], &cm, &cn, &cj, nullptr);
+    logf(1, "batch %p class %zu: %d image(s) of %d x %d, J = %d, plan %p", (void*)b, c, b->cls_images[c], cm, cn, cj,
+         (void*)b->plans[c]);
+  }
   return FFST_OK;
 }
 
@@ -349,6 +359,7 @@ int ffst_batch_inverse(ffst_batch* b, const float* coeffs, float* f, void* ws, v
 }
 
 int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, void* ws, void* stream) {
+  const Range range("ffst_batch_tune");
   if (!batch_ok(b)) return fail(FFST_EBADPLAN, "invalid batch");
   if (!f || !coeffs || !out || !ws) return fail(FFST_EINVAL, "ffst_batch_tune: buffers must be non-NULL");
   // Every class is tuned on its own; the classes then run side by side, so
@@ -368,11 +379,15 @@ int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, vo
     for (size_t c = 0; c < nc; ++c) ffst_set_tuning_ex(b->plans[c], &saved[c]);
     drop_graphs(b);
   }
+  if (st == FFST_OK)
+    logf(1, "batch %p tuned: %.4f ms before, %.4f ms with the classes' own settings; %s", (void*)b, before, after,
+         after > before ? "kept the previous settings" : "kept the tuned settings");
   return st;
 }
 
 void ffst_batch_destroy(ffst_batch* b) {
   if (!batch_ok(b)) return;
+  logf(1, "batch %p destroyed", (void*)b);
   (void)hipDeviceSynchronize();
   free_batch(b);
 }

@@ -191,8 +191,25 @@ struct AllocScope {
 };
 
 // Error reporting shared by the C ABI files: stores the message returned by
-// ffst_last_error on this thread and returns `status`.
+// ffst_last_error on this thread (and writes it to the FFST_LOG log) and
+// returns `status`.
 int fail(int status, const char* fmt, ...);
+
+// Text log selected by the FFST_LOG environment variable (read once):
+// unset, empty or 0 = off; 1 = plans, batches, tuning and errors; 2 = also
+// every transform call; "<level>:<path>" or a bare path (level 1) appends to
+// that file instead of stderr. Lines are written whole, under a lock.
+int log_level();
+void logf(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// roctx range over a scope (shown on rocprofv3 --marker-trace timelines;
+// nearly free when no profiler is attached). `name` must outlive the scope.
+struct Range {
+  explicit Range(const char* name);
+  ~Range();
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 // While set, kernel timing is skipped (launches being captured into a graph).
 void profile_suspend(bool on);
 }  // namespace ffst

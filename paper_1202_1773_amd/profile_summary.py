@@ -23,6 +23,12 @@ of a known size), then averaged per launch of each labelled kernel shape:
 Each label maps a kernel name of the library's timing table to a compiled
 kernel and a grid size in workgroups; one "TRAFFIC {json}" line is printed
 per label, tied to the kernel sources by their hash.
+
+Host-side roctx ranges of the library (one per C ABI call and one per kernel
+launch, named as in its timing table) from a run with --marker-trace and CSV
+output, by median duration:
+
+    python -m paper_1202_1773_amd.profile_summary --markers <dir>
 """
 
 import argparse
@@ -136,16 +142,38 @@ def valu(run_dir, labels):
     return "\n".join(lines)
 
 
+def markers(run_dir):
+    paths = glob.glob(os.path.join(run_dir, "**", "*marker_api_trace.csv"), recursive=True)
+    if not paths:
+        raise RuntimeError(f"no marker trace under {run_dir}")
+    durs = collections.defaultdict(list)
+    for path in paths:
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Function") or row.get("Name") or ""
+                start, end = row.get("Start_Timestamp"), row.get("End_Timestamp")
+                if name and start and end:
+                    durs[name].append((int(end) - int(start)) / 1e3)
+    lines = ["| range | calls | median us | min us | max us |", "|---|---|---|---|---|"]
+    for name, v in sorted(durs.items(), key=lambda kv: -sorted(kv[1])[len(kv[1]) // 2]):
+        v = sorted(v)
+        lines.append(f"| {name} | {len(v)} | {v[len(v) // 2]:.1f} | {v[0]:.1f} | {v[-1]:.1f} |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
     ap.add_argument("--pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--valu", metavar="DIR")
+    ap.add_argument("--markers", metavar="DIR")
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--workload", type=int, nargs=4, metavar=("M", "N", "J", "B"))
     ap.add_argument("--label", action="append", default=[])
     args = ap.parse_args()
-    if args.valu:
+    if args.markers:
+        print(markers(args.markers))
+    elif args.valu:
         print(valu(args.valu, args.label))
     elif args.pmc:
         from .build import source_sha
