@@ -33,23 +33,23 @@ struct ffst_plan {
   int* d_img_lo = nullptr;      // single full window for image-sized passes
   int* d_img_w = nullptr;
   long long* d_img_off = nullptr;
-  int2* d_lines = nullptr;      // forward column lines (spectrum, column), by spectrum
-  // real shearlets: every window column line of Psi_i over its cyclic nonzero
-  // hull (see FwdColArgs), for the CSR entries of both column passes
+  // every window column line of Psi_i (real) or Psi+_i (complex) over its
+  // cyclic nonzero hull (see FwdColArgs), for the CSR entries of both column
+  // passes
   float* psic = nullptr;
   int4* d_col_hull = nullptr;
   int* d_col_ptr = nullptr;     // per plane group: columns -> spectra (CSR, absolute pointers)
   int* d_col_planes = nullptr;
-  // complex shearlets: compact one-sided spectra over cyclic full-plane windows
+  // complex shearlets: compact one-sided spectra over cyclic full-plane
+  // windows (kept for ffst_get_spectra)
   float* psip = nullptr;        // plane i: w[i] columns of M values at psip + poff[i]
   long long* d_poff = nullptr;
-  int2* d_col_ent = nullptr;    // adjoint CSR entries (spectrum, 4 * window column + flags)
+  int2* d_col_ent = nullptr;    // column-pass CSR entries (spectrum, 4 * window column + flags)
   // host copies
   std::vector<int> lo, w;
   std::vector<long long> off;
   std::vector<long long> poff;
   long long zimg = 0;           // complex elements of one image's compact buffer
-  std::vector<int> line_ptr;    // first forward line of each spectrum (eta + 1)
   std::vector<int> groups;      // plane-group boundaries p0 < p1 < ... (ngroups + 1)
   long long chunk_elems = 0;    // target size of one unit's compact buffer
   int tune_nparts = 0;          // lines per column in the adjoint column pass (0: heuristic)
@@ -139,7 +139,7 @@ bool plan_ok(const ffst_plan* p) { return p && p->magic == kMagic; }
 
 // ---- kernel timing -----------------------------------------------------
 const char* kKernelNames[KID_COUNT] = {
-    "k_spectra", "k_windows", "k_r2c_rows(image)", "k_col_fft(image)", "k_fwd_cols",
+    "k_spectra", "k_windows", "k_r2c_rows(image)", "k_fwd_cols",
     "k_c2r_rows(planes)", "k_r2c_rows(planes)", "k_adj_cols", "k_col_fft(inverse)",
     "k_c2r_rows(image)", "k_expand", "k_one_sided", "k_fwd_cols(complex)", "k_c2c_rows(planes, inverse)",
     "k_c2c_rows(planes)", "k_adj_cols(complex)"};
@@ -259,7 +259,7 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
-                  p->d_img_off, p->d_lines, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent,
+                  p->d_img_off, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent,
                   p->psic, p->d_col_hull};
   for (void* b : bufs)
     if (b) release(b);
@@ -476,31 +476,49 @@ void cyclic_hull(const float* col, int M, int* lo, int* K) {
   *K = M - best;
 }
 
-// Psi_i over the hulls of its window column lines: values appended to psic,
-// one (r_lo, K, offset) per line in plane order (hull_of[base[i] + c - lo_i]).
+// Column lines of M values (host copy) over their hulls: values appended to
+// psic, one (r_lo, K, offset) per line appended to hull_of.
+hipError_t line_hulls(const float* lines, long long nlines, int M, std::vector<float>& psic,
+                      std::vector<int4>& hull_of) {
+  for (long long l = 0; l < nlines; ++l) {
+    const float* col = lines + l * M;
+    int lo = 0, K = 0;
+    cyclic_hull(col, M, &lo, &K);
+    if (psic.size() + (size_t)K > (size_t)INT32_MAX) return hipErrorInvalidValue;
+    hull_of.push_back(make_int4(lo, K, (int)psic.size(), 0));
+    for (int k = 0; k < K; ++k) psic.push_back(col[(lo + k) % M]);
+  }
+  return hipSuccess;
+}
+
+// Psi_i over the hulls of its window column lines, in plane order: the line
+// of window column m of plane i is hull_of[base[i] + m]. Real plans read the
+// half-plane spectra, complex plans the one-sided ones (stored by window
+// line already).
 hipError_t spectrum_hulls(const ffst_plan* p, std::vector<float>& psic, std::vector<int4>& hull_of,
                           std::vector<long long>& base) {
   const int M = p->M;
+  const bool cplx = p->opt.complex_shearlets == 1;
   base.assign(p->eta + 1, 0);
+  for (int i = 0; i < p->eta; ++i) base[i + 1] = base[i] + p->w[i];
   std::vector<float> buf;
-  for (int i = 0; i < p->eta; ++i) {
-    base[i + 1] = base[i] + p->w[i];
-    if (p->w[i] == 0) continue;
-    buf.resize((size_t)p->w[i] * M);
-    const hipError_t e = hipMemcpy(buf.data(), p->psi + ((size_t)i * p->H + p->lo[i]) * M, buf.size() * sizeof(float),
-                                   hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return e;
-    for (int m = 0; m < p->w[i]; ++m) {
-      const float* col = buf.data() + (size_t)m * M;
-      int lo = 0, K = 0;
-      cyclic_hull(col, M, &lo, &K);
-      if (psic.size() + (size_t)K > (size_t)INT32_MAX) return hipErrorInvalidValue;
-      hull_of.push_back(make_int4(lo, K, (int)psic.size(), 0));
-      for (int k = 0; k < K; ++k) psic.push_back(col[(lo + k) % M]);
+  hipError_t e = hipSuccess;
+  if (cplx) {
+    buf.resize((size_t)base[p->eta] * M);
+    if (!buf.empty())
+      e = hipMemcpy(buf.data(), p->psip, buf.size() * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = line_hulls(buf.data(), base[p->eta], M, psic, hull_of);
+  } else {
+    for (int i = 0; i < p->eta && e == hipSuccess; ++i) {
+      if (p->w[i] == 0) continue;
+      buf.resize((size_t)p->w[i] * M);
+      e = hipMemcpy(buf.data(), p->psi + ((size_t)i * p->H + p->lo[i]) * M, buf.size() * sizeof(float),
+                    hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = line_hulls(buf.data(), p->w[i], M, psic, hull_of);
     }
   }
   if (psic.empty()) psic.push_back(0.f);
-  return hipSuccess;
+  return e;
 }
 
 Windows plane_windows(const ffst_plan* p) { return Windows{p->d_lo, p->d_w, p->d_off}; }
@@ -662,16 +680,11 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   // Real shearlets: half-plane columns [lo, lo + w). Complex shearlets:
   // cyclic full-plane columns (lo + m) mod N, m < w.
   p->off.assign(p->eta, 0);
-  p->line_ptr.assign(p->eta + 1, 0);
-  std::vector<int2> lines;
   long long acc = 0;
   for (int i = 0; i < p->eta; ++i) {
     p->off[i] = acc;
     acc += (long long)p->pitch * p->w[i];
-    p->line_ptr[i] = (int)lines.size();
-    for (int m = 0; m < p->w[i]; ++m) lines.push_back(make_int2(i, cplx ? m : p->lo[i] + m));
   }
-  p->line_ptr[p->eta] = (int)lines.size();
   p->zimg = acc;
 
   // Plane groups: consecutive spectra whose compact buffer for one image
@@ -691,21 +704,13 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   }
   p->groups.push_back(p->eta);
   const int ngroups = (int)p->groups.size() - 1;
-  // Within a group, order the forward lines by the column of F they read so
-  // that the lines that read the same column run next to each other.
-  auto f_col = [p, cplx](const int2& l) {
-    if (!cplx) return l.y;
-    const int c = (p->lo[l.x] + l.y) % p->N;
-    return c <= p->N / 2 ? c : p->N - c;
-  };
-  for (int g = 0; g < ngroups; ++g)
-    std::stable_sort(lines.begin() + p->line_ptr[p->groups[g]], lines.begin() + p->line_ptr[p->groups[g + 1]],
-                     [&](const int2& a, const int2& b) { return f_col(a) < f_col(b); });
 
-  // Adjoint: half-plane column -> spectra whose window holds it, one CSR per
-  // plane group. Complex shearlets: entries (i, 4 m + flags) for the window
-  // column m that is c (flag 1) or N - c (flag 2); both flags when c = N - c
-  // mod N.
+  // Column passes: half-plane column -> spectra whose window holds it, one
+  // CSR per plane group. Complex shearlets: entries (i, 4 m + flags) for the
+  // window column m that is c (flag 1) or N - c (flag 2); both flags when
+  // c = N - c mod N. In each column the entries with flag 1 or 3 come first
+  // (the forward turns its column of the image spectrum into that of N - c
+  // once, before the first entry with flag 2).
   std::vector<int> col_ptr, col_planes;
   std::vector<int2> col_ent;
   for (int g = 0; g < ngroups; ++g) {
@@ -719,38 +724,43 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
         }
         const int c2 = (p->N - c) % p->N;
         const int m1 = ((c - p->lo[i]) % p->N + p->N) % p->N;
-        const int m2 = ((c2 - p->lo[i]) % p->N + p->N) % p->N;
-        if (c2 == c) {
-          if (m1 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m1 + 3));
-        } else {
-          if (m1 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m1 + 1));
-          if (m2 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m2 + 2));
-        }
+        if (m1 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m1 + (c2 == c ? 3 : 1)));
       }
+      if (cplx)
+        for (int i = p->groups[g]; i < p->groups[g + 1]; ++i) {
+          const int c2 = (p->N - c) % p->N;
+          const int m2 = ((c2 - p->lo[i]) % p->N + p->N) % p->N;
+          if (p->w[i] > 0 && c2 != c && m2 < p->w[i]) col_ent.push_back(make_int2(i, 4 * m2 + 2));
+        }
       col_ptr.push_back(cplx ? (int)col_ent.size() : (int)col_planes.size());
     }
   }
   std::vector<float> psic;
   std::vector<int4> col_hull;
-  if (!cplx) {
+  {
     std::vector<int4> hull_of;
     std::vector<long long> hbase;
     if ((e = spectrum_hulls(p, psic, hull_of, hbase)) != hipSuccess) {
       free_plan(p);
       return fail(e == hipErrorOutOfMemory ? FFST_ENOMEM : FFST_EDEVICE, "spectrum hulls: %s", hipGetErrorString(e));
     }
-    auto hull = [&](int i, int c) { return hull_of[hbase[i] + (c - p->lo[i])]; };
-    for (int g = 0; g < ngroups; ++g)
-      for (int c = 0; c < p->H; ++c)
-        for (int t = col_ptr[g * (p->H + 1) + c]; t < col_ptr[g * (p->H + 1) + c + 1]; ++t)
-          col_hull.push_back(hull(col_planes[t], c));
+    if (cplx) {
+      for (const int2& en : col_ent) col_hull.push_back(hull_of[hbase[en.x] + (en.y >> 2)]);
+    } else {
+      for (int g = 0; g < ngroups; ++g)
+        for (int c = 0; c < p->H; ++c)
+          for (int t = col_ptr[g * (p->H + 1) + c]; t < col_ptr[g * (p->H + 1) + c + 1]; ++t) {
+            const int i = col_planes[t];
+            col_hull.push_back(hull_of[hbase[i] + (c - p->lo[i])]);
+          }
+    }
   }
   std::vector<int> img_lo{0}, img_w{p->H};
   std::vector<long long> img_off{0};
   if ((!p->d_lo && (e = upload(&p->d_lo, p->lo)) != hipSuccess) ||
       (!p->d_w && (e = upload(&p->d_w, p->w)) != hipSuccess) || (e = upload(&p->d_off, p->off)) != hipSuccess || (e = upload(&p->d_img_lo, img_lo)) != hipSuccess ||
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
-      (e = upload(&p->d_lines, lines)) != hipSuccess || (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
+      (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
       (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess ||
       (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_col_hull, col_hull)) != hipSuccess) {
     free_plan(p);
@@ -766,7 +776,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
          (void*)p, M, N, J, p->eta, o.complex_shearlets ? "complex" : "real",
          o.shearlet == FFST_SHEARLET_MEYER_SMOOTH ? "smooth Meyer" : "Meyer", o.aux_order,
          o.max_scale_min ? "'min'" : "'max'", wcols, (long long)p->eta * (o.complex_shearlets ? p->N : p->H),
-         cplx ? (size_t)0 : psic.size(), ngroups, ffst_device_bytes());
+         psic.size(), ngroups, ffst_device_bytes());
   }
   return ok();
 }
@@ -999,11 +1009,9 @@ int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int 
   const long long MN = (long long)p->M * p->N;
   const float scale = (float)(1.0 / ((double)p->M * (double)p->N));
 
+  // row transforms of the images; the column pass completes fft2(f) per column
   RowArgs ra{const_cast<float*>(f), F, MN, MH, 0, batch, 1, 0, p->M, p->N, p->pitch, image_window(p), p->twN};
   hipError_t e = timed(KID_R2C_IMAGE, s, [&] { return launch_r2c_rows(ra, s); });
-  if (e == hipSuccess)
-    e = timed(KID_FFT_COLS_IMAGE, s,
-              [&] { return launch_line_fft(p->M, F, batch * p->H, p->pitch, false, nullptr, 0, 0, p->twM, s); });
   const int ngroups = (int)p->groups.size() - 1;
   for (int img0 = 0; img0 < batch && e == hipSuccess; img0 += sc.chunk_imgs) {
     const int nimg = std::min(sc.chunk_imgs, batch - img0);
@@ -1011,10 +1019,10 @@ int ffst_forward_complex(const ffst_plan* p, const float* f, float* coeffs, int 
       const int p0 = p->groups[g], p1 = p->groups[g + 1];
       const long long base = p->off[p0];
       const long long unit_stride = (p1 < p->eta ? p->off[p1] : p->zimg) - base;
-      CFwdLineArgs fa{p->M, p->N, F + img0 * MH, p->psip, p->d_poff, p->d_lines + p->line_ptr[p0],
-                      p->line_ptr[p1] - p->line_ptr[p0], nimg, p->pitch, plane_windows(p), unit_stride, base, Y,
-                      scale, p->twM};
-      e = timed(KID_FWD_COLS_C, s, [&] { return launch_fwd_lines_c(fa, s); });
+      CFwdColArgs fa{p->M, p->N, F + img0 * MH, p->psic, p->d_col_ptr + g * (p->H + 1), p->d_col_ent,
+                     p->d_col_hull, nimg, sc.fwd_nparts, p->pitch, plane_windows(p), unit_stride, base, Y, scale,
+                     p->twM};
+      e = timed(KID_FWD_COLS_C, s, [&] { return launch_fwd_cols_c(fa, s); });
       if (e != hipSuccess) break;
       CRowArgs rc{C + img0 * p->eta * MN, Y, p->eta * MN, unit_stride, base, nimg, p1 - p0, p0,
                   p->M, p->N, p->pitch, plane_windows(p), p->twN};
@@ -1055,8 +1063,8 @@ int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int 
                   p->M, p->N, p->pitch, plane_windows(p), p->twN};
       e = timed(KID_C2C_PLANES_FWD, s, [&] { return launch_c2c_rows_fwd(rr, s); });
       if (e != hipSuccess) break;
-      CAdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psip, p->d_poff,
-                      p->d_col_ptr + g * (p->H + 1), p->d_col_ent, nimg, sc.nparts, g > 0 ? 1 : 0,
+      CAdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psic,
+                      p->d_col_ptr + g * (p->H + 1), p->d_col_ent, p->d_col_hull, nimg, sc.nparts, g > 0 ? 1 : 0,
                       sc.fused ? 1 : 0, p->pitch, sc.fused ? A + img0 * MH : P, scale, p->twM};
       e = timed(KID_ADJ_COLS_C, s, [&] { return launch_adj_lines_c(aa, s); });
     }

@@ -8,11 +8,14 @@
 // of full-plane columns (one lobe, plus the Nyquist values that stay two-
 // sided), so the intermediates Y_i / Z_i hold only those columns.
 //
-// Forward: the image passes of the real transform give F on the half plane;
-// k_fwd_lines_c multiplies each window column of Psi+_i by the matching
-// (possibly mirrored) column of F / (M N) and runs the inverse column FFT into
-// Y_i; k_c2c_rows_inv runs the inverse row FFT over the window columns and
-// writes full complex rows of c_i.
+// Forward: the real transform's image row pass gives the row transforms of
+// f on the half plane; k_fwd_cols_c takes one half-plane column c per unit,
+// completes fft2(f) at c with the column FFT in registers, and for every
+// window column of a Psi+_i that is c or N - c multiplies by that line of
+// Psi+_i / (M N) (read over its hull of nonzero rows) and runs the inverse
+// column FFT into Y_i; column N - c is conj X(-r) of column c, formed once
+// per unit through LDS. k_c2c_rows_inv runs the inverse row FFT over the
+// window columns and writes full complex rows of c_i.
 //
 // Adjoint (for real images): Re sum_i ifft2(Psi+_i fft2(c_i)). With
 // X = sum_i Psi+_i fft2(c_i) this is the inverse DFT of the Hermitian part
@@ -20,8 +23,8 @@
 // turn into the image. k_c2c_rows_fwd runs the forward row FFT of each
 // coefficient row and stores its window columns Z_i; k_adj_lines_c, per
 // half-plane column c, transforms along the column every Z_i column that is
-// c or N - c, multiplies by Psi+_i and accumulates both sums in registers,
-// then forms (X(r, c) + conj X(-r, N - c)) / 2 through LDS.
+// c or N - c, multiplies by Psi+_i (over its hull) and accumulates both sums
+// in registers, then forms (X(r, c) + conj X(-r, N - c)) / 2 through LDS.
 #include "fft_core.hpp"
 #include "internal.hpp"
 #include "launch_cfg.hpp"
@@ -157,12 +160,21 @@ __global__ void __launch_bounds__(CRowCfg<L>::THREADS) k_c2c_rows_fwd(CRowJob jo
   }
 }
 
-struct CFwdLineJob {
-  const float2* F;          // [nimg][H][pitch]
-  const float* psip;
-  const long long* poff;
-  const int2* lines;        // (spectrum, window column m), image lines ordered by the F column they read
-  int nlines, nimg, H, N;
+// Index m of element e of a column line inside the line's cyclic hull
+// [r_lo, r_lo + K) (mod L), or a value >= K when e lies outside it.
+template <int L>
+__device__ __forceinline__ int chull_index(int e, int r_lo) {
+  const int d = e - r_lo;
+  return d < 0 ? d + L : d;
+}
+
+struct CFwdColJob {
+  const float2* F;
+  const float* psic;
+  const int* col_ptr;
+  const int2* col_ent;
+  const int4* col_hull;
+  int H, nimg, nparts;
   int pitch;
   Windows win;
   long long y_img_stride, y_off_base;
@@ -171,53 +183,70 @@ struct CFwdLineJob {
   const float2* twM;
 };
 
-// Y_i[m] = ifft_col(Psi+_i[m] * scale * F[c]) with c = (lo_i + m) mod N; for
-// c > N/2 the column of F is conj F(-r, N - c).
+// Unit (c, img, part): X = fft_col of the row transforms at half-plane
+// column c; then, for every nparts-th entry of the column (from the part's
+// index), Y_i[m] = ifft_col(Psi+_i[m] * scale * X') with X' = X for flags 1
+// and 3 (the window column is c) and X'(r) = conj X(-r) for flag 2 (it is
+// N - c). The column's entries with flag 2 come last, so X is turned into
+// X' once, at the first of them. Units run column-major (the images of one
+// column share its spectrum lines).
 template <int M>
-__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_lines_c(CFwdLineJob job) {
+__global__ void __launch_bounds__(LineCfg<M>::THREADS) k_fwd_cols_c(CFwdColJob job) {
   using C = LineCfg<M>;
   constexpr int V = C::V, G = C::G;
   __shared__ float2 lds[C::LPB * C::STRIDE];
   const int g = group_index<C>();
   const int j = group_lane<C>();
+  float2* my = lds + g * C::STRIDE;
   TwiddleSeeds<M, V> tw;
   tw.load(j, job.twM, 1);
-  const int total = job.nlines * job.nimg;
-  float2 fn[V];
-  float pn[V];
-  // units image by image, lines ordered by the F column they read
-  auto load_unit = [&](int u) {
-    const int q = u * C::LPB + g;
-    const int qq = q < total ? q : 0;
-    const int img = qq / job.nlines;
-    const int2 ln = job.lines[qq % job.nlines];
-    const int c = wrap_once(job.win.lo[ln.x] + ln.y, job.N);
-    const bool upper = c > job.N / 2;
-    const float2* fb = job.F + ((long long)img * job.H + (upper ? job.N - c : c)) * job.pitch;
-    const float* pb = job.psip + job.poff[ln.x] + (long long)ln.y * M;
-#pragma unroll
-    for (int s = 0; s < V; ++s) {
-      const int r = j + G * s;
-      const float2 fv = fb[upper ? mirror_index(r, M) : r];
-      fn[s] = upper ? conjf2(fv) : fv;
-      pn[s] = pb[r];
-    }
-  };
-  int u = blockIdx.x;
-  if (u * C::LPB < total) load_unit(u);
-  for (; u * C::LPB < total; u += gridDim.x) {
+  const int total = job.H * job.nimg * job.nparts;
+  for (int u = blockIdx.x; u * C::LPB < total; u += gridDim.x) {
     const int q = u * C::LPB + g;
     const bool ok = q < total;
     const int qq = ok ? q : 0;
-    const int img = qq / job.nlines;
-    const int2 ln = job.lines[qq % job.nlines];
-    float2 v[V];
+    const int part = qq % job.nparts;
+    const int rest = qq / job.nparts;
+    const int img = rest % job.nimg;
+    const int c = rest / job.nimg;
+    const float2* fb = job.F + ((long long)img * job.H + c) * job.pitch;
+    float2 x[V];
 #pragma unroll
-    for (int s = 0; s < V; ++s) v[s] = cscale(fn[s], pn[s] * job.scale);
-    if ((u + (int)gridDim.x) * C::LPB < total) load_unit(u + gridDim.x);
-    fft_group<M, V, true, C::SYNC>(v, j, lds + g * C::STRIDE, tw);
-    if (ok) {
-      float2* yb = job.Y + img * job.y_img_stride + (job.win.off[ln.x] - job.y_off_base) + (long long)ln.y * job.pitch;
+    for (int s = 0; s < V; ++s) x[s] = fb[j + G * s];
+    fft_group<M, V, false, C::SYNC>(x, j, my, tw);
+    float2* yimg = job.Y + img * job.y_img_stride - job.y_off_base;
+    const int q1 = ok ? job.col_ptr[c + 1] : 0;
+    int t = job.col_ptr[c] + part;
+    bool mirrored = false;
+    float pn[V];
+    auto load_psi = [&](int tt) {
+      const int4 hl = job.col_hull[tt];
+      const float* pb = job.psic + hl.z;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        const int m = chull_index<M>(j + G * s, hl.x);
+        pn[s] = m < hl.y ? pb[m] * job.scale : 0.f;
+      }
+    };
+    if (t < q1) load_psi(t);
+    for (; t < q1; t += job.nparts) {
+      const int2 e = job.col_ent[t];
+      if ((e.y & 3) == 2 && !mirrored) {
+        // X'(r) = conj X(-r mod M), through the group's LDS
+#pragma unroll
+        for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = x[s];
+        lds_sync<C::SYNC>();
+#pragma unroll
+        for (int s = 0; s < V; ++s) x[s] = conjf2(my[lpad<V>(mirror_index(j + G * s, M))]);
+        lds_sync<C::SYNC>();
+        mirrored = true;
+      }
+      float2 v[V];
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cscale(x[s], pn[s]);
+      if (t + job.nparts < q1) load_psi(t + job.nparts);
+      fft_group<M, V, true, C::SYNC>(v, j, my, tw);
+      float2* yb = yimg + job.win.off[e.x] + (long long)(e.y >> 2) * job.pitch;
 #pragma unroll
       for (int s = 0; s < V; ++s) yb[j + G * s] = v[s];
     }
@@ -228,10 +257,10 @@ struct CAdjLineJob {
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psip;
-  const long long* poff;
+  const float* psic;
   const int* col_ptr;
   const int2* col_ent;
+  const int4* col_hull;
   int H, nimg, nparts;
   int pitch;
   int accumulate;
@@ -273,14 +302,15 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
     int fn = 0;
     auto load_entry = [&](int tt) {
       const int2 e = job.col_ent[tt];
-      const int m = e.y >> 2;
+      const int4 hl = job.col_hull[tt];
       fn = e.y & 3;
-      const float2* zb = zimg + job.win.off[e.x] + (long long)m * job.pitch;
-      const float* pb = job.psip + job.poff[e.x] + (long long)m * M;
+      const float2* zb = zimg + job.win.off[e.x] + (long long)(e.y >> 2) * job.pitch;
+      const float* pb = job.psic + hl.z;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         zn[s] = zb[j + G * s];
-        pn[s] = pb[j + G * s];
+        const int m = chull_index<M>(j + G * s, hl.x);
+        pn[s] = m < hl.y ? pb[m] : 0.f;
       }
     };
     if (t < q1) load_entry(t);
@@ -401,16 +431,17 @@ hipError_t launch_c2c_rows_fwd(const CRowArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t launch_fwd_lines_c(const CFwdLineArgs& a, hipStream_t s) {
-  CFwdLineJob job{a.F, a.psip, a.poff, a.lines, a.nlines, a.nimg, a.N / 2 + 1, a.N, a.pitch, a.win,
-                  a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
-  if (job.nlines == 0 || job.nimg == 0) return hipSuccess;
-  const long long total = (long long)job.nlines * job.nimg;
+hipError_t launch_fwd_cols_c(const CFwdColArgs& a, hipStream_t s) {
+  CFwdColJob job{a.F, a.psic, a.col_ptr, a.col_ent, a.col_hull, a.N / 2 + 1, a.nimg, a.nparts, a.pitch, a.win,
+                 a.y_img_stride, a.y_off_base, a.Y, a.scale, a.twM};
+  if (job.nimg == 0) return hipSuccess;
+  if (job.nparts < 1) return hipErrorInvalidValue;
+  const long long total = (long long)job.H * job.nimg * job.nparts;
   switch (a.M) {
 #define CASE(n)                                                                                   \
   case n: {                                                                                       \
     const long long units = (total + LineCfg<n>::LPB - 1) / LineCfg<n>::LPB;                      \
-    hipLaunchKernelGGL(k_fwd_lines_c<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),              \
+    hipLaunchKernelGGL(k_fwd_cols_c<n>, dim3(grid_for(units, LineCfg<n>::THREADS)),               \
                        dim3(LineCfg<n>::THREADS), 0, s, job);                                     \
     return hipGetLastError();                                                                     \
   }
@@ -421,7 +452,7 @@ hipError_t launch_fwd_lines_c(const CFwdLineArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_adj_lines_c(const CAdjLineArgs& a, hipStream_t s) {
-  CAdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psip, a.poff, a.col_ptr, a.col_ent, a.N / 2 + 1,
+  CAdjLineJob job{a.Z, a.z_img_stride, a.z_off_base, a.win, a.psic, a.col_ptr, a.col_ent, a.col_hull, a.N / 2 + 1,
                   a.nimg, a.nparts, a.pitch, a.accumulate, a.out, a.scale, a.twM};
   if (job.nimg == 0) return hipSuccess;
   const long long total = (long long)job.H * job.nimg * job.nparts;

@@ -29,7 +29,6 @@ enum KernelId : int {
   KID_SPECTRA = 0,
   KID_WINDOWS,
   KID_R2C_IMAGE,
-  KID_FFT_COLS_IMAGE,
   KID_FWD_COLS,
   KID_C2R_PLANES,
   KID_R2C_PLANES,
@@ -147,13 +146,15 @@ hipError_t launch_c2c_rows_inv(const CRowArgs& a, hipStream_t s);
 // Forward row FFT of full complex rows, storing the window columns.
 hipError_t launch_c2c_rows_fwd(const CRowArgs& a, hipStream_t s);
 
-struct CFwdLineArgs {
+struct CFwdColArgs {
   int M, N;
-  const float2* F;          // half-plane image spectra [nimg][N/2+1][pitch]
-  const float* psip;
-  const long long* poff;
-  const int2* lines;        // (spectrum, window column m)
-  int nlines, nimg;
+  const float2* F;          // row transforms of the images, half-plane columns [nimg][N/2+1][pitch]
+  const float* psic;        // one-sided spectrum lines over their hulls
+  const int* col_ptr;       // half-plane column -> entries (CSR of this plane group)
+  const int2* col_ent;      // (spectrum, 4 * window column + flags); in each column the
+                            // entries with flag 1 or 3 come before those with flag 2
+  const int4* col_hull;     // hull (first row, length, offset in psic) of every entry's line
+  int nimg, nparts;
   int pitch;
   Windows win;
   long long y_img_stride, y_off_base;
@@ -161,17 +162,21 @@ struct CFwdLineArgs {
   float scale;
   const float2* twM;
 };
-hipError_t launch_fwd_lines_c(const CFwdLineArgs& a, hipStream_t s);
+// Per half-plane column c of every image: column FFT of the row transforms,
+// then ifft_col(Psi+_i[m] * scale * X) into Y_i for every entry of the
+// column, X being the image spectrum's column c (flags 1, 3) or full-plane
+// column N - c (flag 2: conj X(-r) of column c).
+hipError_t launch_fwd_cols_c(const CFwdColArgs& a, hipStream_t s);
 
 struct CAdjLineArgs {
   int M, N;
   const float2* Z;
   long long z_img_stride, z_off_base;
   Windows win;
-  const float* psip;
-  const long long* poff;
+  const float* psic;        // one-sided spectrum lines over their hulls
   const int* col_ptr;       // half-plane column -> entries (CSR)
   const int2* col_ent;      // (spectrum, 4 * window column + flags), flag 1: column c, 2: column N - c
+  const int4* col_hull;     // hull of every entry's line
   int nimg, nparts, accumulate, fused;
   int pitch;
   float2* out;
