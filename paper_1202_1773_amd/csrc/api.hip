@@ -44,7 +44,10 @@ struct ffst_plan {
   // windows (kept for ffst_get_spectra)
   float* psip = nullptr;        // plane i: w[i] columns of M values at psip + poff[i]
   long long* d_poff = nullptr;
-  int2* d_col_ent = nullptr;    // column-pass CSR entries (spectrum, 4 * window column + flags)
+  int2* d_col_ent = nullptr;    // forward CSR entries (spectrum, 4 * window column + flags)
+  int* d_acol_ptr = nullptr;    // adjoint CSR (complex): columns -> entries with flag 1 or 2,
+  int2* d_acol_ent = nullptr;   //   hulls of the reversed lines for flag 2
+  int4* d_acol_hull = nullptr;
   // host copies
   std::vector<int> lo, w;
   std::vector<long long> off;
@@ -260,7 +263,7 @@ void free_plan(ffst_plan* p) {
   if (!p) return;
   void* bufs[] = {p->psi, p->twM, p->twN, p->d_lo, p->d_w, p->d_off, p->d_img_lo, p->d_img_w,
                   p->d_img_off, p->d_col_ptr, p->d_col_planes, p->psip, p->d_poff, p->d_col_ent,
-                  p->psic, p->d_col_hull};
+                  p->psic, p->d_col_hull, p->d_acol_ptr, p->d_acol_ent, p->d_acol_hull};
   for (void* b : bufs)
     if (b) release(b);
   p->magic = 0;
@@ -737,6 +740,9 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   }
   std::vector<float> psic;
   std::vector<int4> col_hull;
+  std::vector<int> acol_ptr;
+  std::vector<int2> acol_ent;
+  std::vector<int4> acol_hull;
   {
     std::vector<int4> hull_of;
     std::vector<long long> hbase;
@@ -746,6 +752,43 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     }
     if (cplx) {
       for (const int2& en : col_ent) col_hull.push_back(hull_of[hbase[en.x] + (en.y >> 2)]);
+      // Adjoint table: the same windows, an entry for column N - c carrying
+      // the hull of its line reversed (Psi(-r)); a window column with
+      // c = N - c is listed once with each flag.
+      const int M = p->M;
+      auto reversed = [&](int i, int m) {
+        const int4 h = hull_of[hbase[i] + m];
+        const int off = (int)psic.size();
+        for (int k = 0; k < h.y; ++k) {
+          const float v = psic[(size_t)h.z + h.y - 1 - k];
+          psic.push_back(v);
+        }
+        return make_int4(((M - h.x - h.y + 1) % M + M) % M, h.y, off, 0);
+      };
+      for (int g = 0; g < ngroups; ++g) {
+        acol_ptr.push_back((int)acol_ent.size());
+        for (int c = 0; c < p->H; ++c) {
+          const int c2 = (p->N - c) % p->N;
+          for (int i = p->groups[g]; i < p->groups[g + 1]; ++i) {
+            if (p->w[i] == 0) continue;
+            const int m1 = ((c - p->lo[i]) % p->N + p->N) % p->N;
+            const int m2 = ((c2 - p->lo[i]) % p->N + p->N) % p->N;
+            if (m1 < p->w[i]) {
+              acol_ent.push_back(make_int2(i, 4 * m1 + 1));
+              acol_hull.push_back(hull_of[hbase[i] + m1]);
+            }
+            if (m2 < p->w[i]) {
+              acol_ent.push_back(make_int2(i, 4 * m2 + 2));
+              acol_hull.push_back(reversed(i, m2));
+            }
+          }
+          acol_ptr.push_back((int)acol_ent.size());
+        }
+      }
+      if (psic.size() > (size_t)INT32_MAX) {
+        free_plan(p);
+        return fail(FFST_EUNSUPPORTED, "spectrum hulls exceed 2^31 values");
+      }
     } else {
       for (int g = 0; g < ngroups; ++g)
         for (int c = 0; c < p->H; ++c)
@@ -762,7 +805,9 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       (e = upload(&p->d_img_w, img_w)) != hipSuccess || (e = upload(&p->d_img_off, img_off)) != hipSuccess ||
       (e = upload(&p->d_col_ptr, col_ptr)) != hipSuccess ||
       (e = upload(&p->d_col_planes, col_planes)) != hipSuccess || (e = upload(&p->d_col_ent, col_ent)) != hipSuccess ||
-      (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_col_hull, col_hull)) != hipSuccess) {
+      (e = upload(&p->psic, psic)) != hipSuccess || (e = upload(&p->d_col_hull, col_hull)) != hipSuccess ||
+      (e = upload(&p->d_acol_ptr, acol_ptr)) != hipSuccess || (e = upload(&p->d_acol_ent, acol_ent)) != hipSuccess ||
+      (e = upload(&p->d_acol_hull, acol_hull)) != hipSuccess) {
     free_plan(p);
     return fail(FFST_ENOMEM, "plan tables: %s", hipGetErrorString(e));
   }
@@ -1064,7 +1109,7 @@ int ffst_adjoint_complex(const ffst_plan* p, const float* coeffs, float* f, int 
       e = timed(KID_C2C_PLANES_FWD, s, [&] { return launch_c2c_rows_fwd(rr, s); });
       if (e != hipSuccess) break;
       CAdjLineArgs aa{p->M, p->N, Z, unit_stride, base, plane_windows(p), p->psic,
-                      p->d_col_ptr + g * (p->H + 1), p->d_col_ent, p->d_col_hull, nimg, sc.nparts, g > 0 ? 1 : 0,
+                      p->d_acol_ptr + g * (p->H + 1), p->d_acol_ent, p->d_acol_hull, nimg, sc.nparts, g > 0 ? 1 : 0,
                       sc.fused ? 1 : 0, p->pitch, sc.fused ? A + img0 * MH : P, scale, p->twM};
       e = timed(KID_ADJ_COLS_C, s, [&] { return launch_adj_lines_c(aa, s); });
     }

@@ -269,9 +269,14 @@ struct CAdjLineJob {
   const float2* twM;
 };
 
-// Line (img, c, part): X1 = sum Psi+_i[m] fft_col(Z_i[m]) over the entries
-// whose column is c, X2 the same over the entries whose column is N - c
-// (part p takes every nparts-th entry); A[c](r) = scale * (X1(r) + conj X2(-r)).
+// Line (img, c, part): A[c](r) = scale * (X1(r) + conj X2(-r)), X1 the sum
+// of Psi+_i[m] fft_col(Z_i[m]) over the windows that hold column c, X2 the
+// same over those that hold N - c (part p takes every nparts-th entry). The
+// second sum is accumulated directly: conj (Psi X)(-r) = Psi(-r)
+// fft_col(conj z)(r) for a real Psi and X = fft_col(z), so an entry for
+// column N - c (flag 2) transforms the conjugated line and carries the
+// spectrum line reversed (Psi(-r), stored so at plan creation). A window
+// column with c = N - c enters the adjoint's table twice, once each way.
 template <int M, bool FUSED>
 __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
   using C = LineCfg<M>;
@@ -291,9 +296,9 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
     const int rest = qq / job.nparts;
     const int img = rest % job.nimg;
     const int c = rest / job.nimg;
-    float2 acc1[V], acc2[V];
+    float2 acc[V];
 #pragma unroll
-    for (int s = 0; s < V; ++s) acc1[s] = acc2[s] = make_float2(0.f, 0.f);
+    for (int s = 0; s < V; ++s) acc[s] = make_float2(0.f, 0.f);
     const float2* zimg = job.Z + img * job.z_img_stride - job.z_off_base;
     const int q1 = ok ? job.col_ptr[c + 1] : 0;
     int t = job.col_ptr[c] + part;
@@ -320,40 +325,31 @@ __device__ __forceinline__ void adj_lines_c_body(const CAdjLineJob& job) {
       const int fl = fn;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
-        v[s] = zn[s];
+        v[s] = fl == 2 ? conjf2(zn[s]) : zn[s];
         ps[s] = pn[s];
       }
       if (t + job.nparts < q1) load_entry(t + job.nparts);
       fft_group<M, V, false, C::SYNC>(v, j, my, tw);
 #pragma unroll
       for (int s = 0; s < V; ++s) {
-        const float2 pv = cscale(v[s], ps[s]);
-        if (fl & 1) acc1[s] = cadd(acc1[s], pv);
-        if (fl & 2) acc2[s] = cadd(acc2[s], pv);
+        acc[s].x += ps[s] * v[s].x;
+        acc[s].y += ps[s] * v[s].y;
       }
     }
-    // Hermitian part: acc1(r) + conj acc2(-r mod M)
 #pragma unroll
-    for (int s = 0; s < V; ++s) my[lpad<V>(j + G * s)] = acc2[s];
-    lds_sync<C::SYNC>();
-#pragma unroll
-    for (int s = 0; s < V; ++s) {
-      const float2 rv = my[lpad<V>(mirror_index(j + G * s, M))];
-      acc1[s] = cscale(cadd(acc1[s], conjf2(rv)), job.scale);
-    }
-    lds_sync<C::SYNC>();
+    for (int s = 0; s < V; ++s) acc[s] = cscale(acc[s], job.scale);
     if constexpr (FUSED) {
-      fft_group<M, V, true, C::SYNC>(acc1, j, my, tw);
+      fft_group<M, V, true, C::SYNC>(acc, j, my, tw);
       if (ok) {
         float2* ab = job.out + ((long long)img * job.H + c) * job.pitch;
 #pragma unroll
-        for (int s = 0; s < V; ++s) ab[j + G * s] = acc1[s];
+        for (int s = 0; s < V; ++s) ab[j + G * s] = acc[s];
       }
     } else if (ok) {
       float2* pb = job.out + (((long long)part * job.nimg + img) * job.H + c) * job.pitch;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
-        float2 val = acc1[s];
+        float2 val = acc[s];
         if (job.accumulate) val = cadd(val, pb[j + G * s]);
         pb[j + G * s] = val;
       }

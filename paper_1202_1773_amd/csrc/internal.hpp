@@ -174,9 +174,10 @@ struct CAdjLineArgs {
   long long z_img_stride, z_off_base;
   Windows win;
   const float* psic;        // one-sided spectrum lines over their hulls
-  const int* col_ptr;       // half-plane column -> entries (CSR)
-  const int2* col_ent;      // (spectrum, 4 * window column + flags), flag 1: column c, 2: column N - c
-  const int4* col_hull;     // hull of every entry's line
+  const int* col_ptr;       // half-plane column -> entries (CSR of the adjoint)
+  const int2* col_ent;      // (spectrum, 4 * window column + flag), flag 1: column c, 2: column N - c
+                            // (a column c = N - c appears once with each flag)
+  const int4* col_hull;     // hull of every entry's line; for flag 2 that of the reversed line Psi(-r)
   int nimg, nparts, accumulate, fused;
   int pitch;
   float2* out;
