@@ -49,21 +49,21 @@ METRIC = "Gcoef/s fwd+adjoint @512² J=3 FP32 (%HBM roofline); batched vs plain"
 
 
 def committed_traffic(kernel, M, N, J, B):
-    """HBM bytes per launch of `kernel` from profiles/traffic_*.md, if that
-    summary was measured on the current kernel sources and this workload."""
-    path = os.path.join(ROOT, "profiles", "traffic_ffst_512x512_J3_B16.md")
-    if not os.path.exists(path):
-        return None
+    """HBM bytes per launch of `kernel` from the profiles/traffic_*.md
+    summaries, if one was measured on the current kernel sources and this
+    workload."""
+    import glob
     want = source_sha()
-    for line in open(path):
-        if line.startswith("TRAFFIC {"):
-            try:
-                rec = json.loads(line[len("TRAFFIC "):])
-            except ValueError:
-                continue
-            if (rec.get("kernel") == kernel and rec.get("source_sha") == want
-                    and rec.get("workload") == [M, N, J, B]):
-                return rec["bytes_per_launch"]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        for line in open(path):
+            if line.startswith("TRAFFIC {"):
+                try:
+                    rec = json.loads(line[len("TRAFFIC "):])
+                except ValueError:
+                    continue
+                if (rec.get("kernel") == kernel and rec.get("source_sha") == want
+                        and rec.get("workload") == [M, N, J, B]):
+                    return rec["bytes_per_launch"]
     return None
 
 
@@ -153,6 +153,54 @@ def time_steps(step, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+# Algorithmic bytes per step of the coefficient row passes: every
+# coefficient of the step is read (adjoint) or written (forward) once.
+COEF_PASSES = {"k_c2r_rows(planes)": 4, "k_r2c_rows(planes)": 4,
+               "k_c2c_rows(planes, inverse)": 8, "k_c2c_rows(planes)": 8}
+
+
+def leg_roofline(step, steps, coefs_per_step, workload=None):
+    """The dominant kernel of a leg's step (found with HIP events, one kernel
+    per short pass) and its average launch duration over `steps` steps with
+    only that kernel bracketed. For a coefficient row pass, achieved =
+    algorithmic bytes per launch (coefficients of the step x bytes each /
+    launches per step) over that duration; for other kernels the duration
+    only; `traffic` from a committed counter summary of this workload
+    (M, N, J, B), if given and measured on the current kernel sources. Graph
+    replays are not timed by the library, so legs that run as graphs do not
+    use this."""
+    import torch
+    from paper_1202_1773_amd import _lib
+
+    per_kernel = {}
+    for k in range(_lib.ffst_num_kernels()):
+        _lib.ffst_profile_reset()
+        _lib.ffst_profile_enable(1 << k)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        ms, n = _lib.ffst_profile_read(k)
+        if n:
+            per_kernel[_lib.ffst_kernel_name(k)] = (ms / 3, n / 3, k)
+    _lib.ffst_profile_enable(0)
+    name, (_, per_step, kid) = max(per_kernel.items(), key=lambda kv: kv[1][0])
+    _lib.ffst_profile_reset()
+    _lib.ffst_profile_enable(1 << kid)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    _lib.ffst_profile_enable(0)
+    ms, n = _lib.ffst_profile_read(kid)
+    avg = ms / max(n, 1)
+    out = {"kernel": name, "avg_launch_ms": round(avg, 5), "launches_per_step": round(per_step, 2)}
+    if name in COEF_PASSES:
+        alg = COEF_PASSES[name] * coefs_per_step / per_step
+        out.update({"bound": "hbm", "alg_bytes_per_launch": int(alg), "achieved": round(alg / avg / 1e6, 2),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / avg / 1e6 / HBM_PEAK_GBS, 4),
+                    "traffic": committed_traffic(name, *workload) if workload else None})
+    return out
+
+
 def bench_uneven(steps, warmup, tune):
     """The uneven batch: 64 images drawn from 256^2 .. 1024^2 (seed 401), one
     graph launch per direction; forward + adjoint per step."""
@@ -216,10 +264,11 @@ def bench_complex(x, M, N, J, steps, warmup):
     # complex coefficients: 8 bytes each, written then read
     b_alg = 2 * 8 * coef + 2 * 4 * B * M * N + 2 * 4 * int((plan.spectra(full_plane=True) != 0).sum().item())
     rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+    roof = leg_roofline(step, steps, coef, (M, N, J, B))
     plan.close()
     return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
             "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
-            "reconstruction_rel_l2": rec}
+            "reconstruction_rel_l2": rec, "roofline": roof}
 
 
 def bench_smooth(x, M, N, J, steps, warmup):
@@ -241,10 +290,13 @@ def bench_smooth(x, M, N, J, steps, warmup):
     coef = B * plan.eta * M * N
     b_alg = 4 * (2 * coef + 2 * B * M * N + 2 * nnz_half(plan))
     rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+    # the headline's kernels with other spectra: the headline's traffic
+    # summary does not apply, so none is looked up
+    roof = leg_roofline(step, steps, coef)
     plan.close()
     return {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
             "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
-            "reconstruction_rel_l2": rec}
+            "reconstruction_rel_l2": rec, "roofline": roof}
 
 
 def bench_denoise(steps, warmup):
@@ -303,7 +355,8 @@ def bench_large(steps, warmup, tune):
     rec = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
     out = {"ms_per_step": round(t * 1e3, 4), "value": round(coef / t / 1e9, 3), "unit": "Gcoef/s",
            "alg_bytes_per_step": b_alg, "path_frac": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 4),
-           "reconstruction_rel_l2": rec, "launch_tuning": plan.tuning_ex()}
+           "reconstruction_rel_l2": rec, "launch_tuning": plan.tuning_ex(),
+           "roofline": leg_roofline(step, steps, coef, (M, N, 5, 1))}
     plan.close()
     return out
 
@@ -321,6 +374,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-batch and complex-shearlet measurements")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch settings only")
+    ap.add_argument("--legs", default="complex_shearlets,uneven_batch,large_image,smooth_shearlets,l1_denoise",
+                    help="comma-separated extra legs to run after the headline (e.g. for profiling one leg)")
     ap.add_argument("--tuning", default=None, metavar="NPARTS,BLOCKS_PER_CU,COL_VALUES,ROW_BLOCK[,FWD_NPARTS]",
                     help="use these launch settings for the batched and plain plans instead of autotuning "
                          "(ffst_tuning in include/ffst.h; for profiling runs that must not sweep)")
@@ -502,11 +557,15 @@ def main():
 
     if not args.no_extras:
         extra_steps = max(3, args.steps // 5)
-        out["complex_shearlets"] = bench_complex(x, M, N, J, extra_steps, 2)
-        out["uneven_batch"] = bench_uneven(extra_steps, 2, not args.no_tune)
-        out["large_image"] = bench_large(extra_steps, 2, not args.no_tune)
-        out["smooth_shearlets"] = bench_smooth(x, M, N, J, extra_steps, 2)
-        out["l1_denoise"] = bench_denoise(extra_steps, 2)
+        legs = {"complex_shearlets": lambda: bench_complex(x, M, N, J, extra_steps, 2),
+                "uneven_batch": lambda: bench_uneven(extra_steps, 2, not args.no_tune),
+                "large_image": lambda: bench_large(extra_steps, 2, not args.no_tune),
+                "smooth_shearlets": lambda: bench_smooth(x, M, N, J, extra_steps, 2),
+                "l1_denoise": lambda: bench_denoise(extra_steps, 2)}
+        for name in [n for n in args.legs.split(",") if n]:
+            if name not in legs:
+                raise SystemExit(f"unknown leg {name!r} (known: {', '.join(legs)})")
+            out[name] = legs[name]()
 
     psi_half = plan.spectra(full_plane=False).cpu().numpy() if not args.no_cpu_baseline else None
     plan.close()
