@@ -487,7 +487,7 @@ hipError_t line_hulls(const float* lines, long long nlines, int M, std::vector<f
     const float* col = lines + l * M;
     int lo = 0, K = 0;
     cyclic_hull(col, M, &lo, &K);
-    if (psic.size() + (size_t)K > (size_t)INT32_MAX) return hipErrorInvalidValue;
+    if (psic.size() + (size_t)K > (size_t)INT32_MAX) return hipErrorNotSupported;   // offsets would overflow
     hull_of.push_back(make_int4(lo, K, (int)psic.size(), 0));
     for (int k = 0; k < K; ++k) psic.push_back(col[(lo + k) % M]);
   }
@@ -748,6 +748,8 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
     std::vector<long long> hbase;
     if ((e = spectrum_hulls(p, psic, hull_of, hbase)) != hipSuccess) {
       free_plan(p);
+      if (e == hipErrorNotSupported)   // offsets into the hull values are 32-bit
+        return fail(FFST_EUNSUPPORTED, "spectrum hulls exceed 2^31 values (%d x %d, J = %d)", M, N, J);
       return fail(e == hipErrorOutOfMemory ? FFST_ENOMEM : FFST_EDEVICE, "spectrum hulls: %s", hipGetErrorString(e));
     }
     if (cplx) {
@@ -787,7 +789,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
       }
       if (psic.size() > (size_t)INT32_MAX) {
         free_plan(p);
-        return fail(FFST_EUNSUPPORTED, "spectrum hulls exceed 2^31 values");
+        return fail(FFST_EUNSUPPORTED, "spectrum hulls exceed 2^31 values (%d x %d, J = %d)", M, N, J);
       }
     } else {
       for (int g = 0; g < ngroups; ++g)
