@@ -383,6 +383,8 @@ struct TwiddleSeeds {
       load_stage<S + 1>(j, table, ts);
     }
   }
+  // The lane index passes through an empty asm, as in TwiddleRegs::load
+  // (without it the length-144 kernels compute wrong twiddles).
   __device__ __forceinline__ void load(int j, const float2* __restrict__ table, int ts) {
     __asm__ __volatile__("" : "+v"(j));
     load_stage<1>(j, table, ts);
