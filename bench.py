@@ -384,8 +384,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only; --gpus must be 1 "
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
