@@ -179,6 +179,29 @@ def test_large_2048_sampled_planes_and_properties():
     plan.close()
 
 
+@pytest.mark.timeout(400)
+def test_large_2048_bench_configuration_sampled():
+    # The benchmark autotunes the 2048 x 2048, J = 5 plan before timing it;
+    # check sampled planes and the reconstruction in the launch shapes the
+    # tuner picks (the FP64 oracle planes take a minute of host time).
+    from paper_1202_1773_amd.synthetic import config5_image
+    log("2048x2048 J=5 after autotuning")
+    f = config5_image()
+    plan = Plan(2048, 2048, 5)
+    x = torch.from_numpy(f).to(_dev())
+    plan.tune(x)
+    log(f"  settings {plan.tuning_ex()}")
+    c = plan.forward(x)
+    planes = [1, 62, 124]
+    err = per_plane_rel_l2(c[planes].cpu().numpy(), oracle_forward(f, 2048, 2048, 5, planes=planes))
+    log(f"  sampled planes relL2 {err}")
+    assert err.max() <= TOL
+    assert rel_l2(plan.adjoint(c).cpu().numpy(), f) <= TOL
+    del c
+    plan.close()
+    torch.cuda.empty_cache()
+
+
 def test_constant_and_zero_batch():
     plan = Plan(64, 64, 2)
     x = torch.full((64, 64), 2.5, device=_dev())
