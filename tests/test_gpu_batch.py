@@ -129,16 +129,22 @@ def test_uneven_batch_odd_and_27_sides():
     bp.close()
 
 
-def test_uneven_workload_64_images():
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("tuned", [False, True])
+def test_uneven_workload_64_images(tuned):
     # the uneven workload: 64 images drawn from 256^2 .. 1024^2 (seed 401),
     # J = 3 up to 512, else 4; one image per size checked on sampled planes,
-    # reconstruction of all 64
-    log("uneven workload, 64 images")
+    # reconstruction of all 64; with the built-in launch settings and after
+    # the batch autotuner (the settings the benchmark times)
+    log(f"uneven workload, 64 images, tuned={tuned}")
     sizes, Js = uneven_sizes()
     imgs = uneven_images(sizes)
     bp = BatchPlan(sizes, Js)
     assert bp.classes == 5
     f = bp.pack([torch.from_numpy(i) for i in imgs])
+    if tuned:
+        bp.tune(f)
+        log(f"  class settings {bp.class_tuning()}")
     c = bp.forward(f)
     views = bp.coefficients(c)
     done = set()
