@@ -74,7 +74,7 @@ int ffst::fail(int status, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
-  logf(1, "error %d: %s", status, buf);
+  log_line(1, "error %d: %s", status, buf);
   return status;
 }
 
@@ -817,7 +817,7 @@ int ffst_spectra_ex(int M, int N, int J, const ffst_options* opt, ffst_plan** ou
   if (log_level() >= 1) {
     long long wcols = 0;
     for (int i = 0; i < p->eta; ++i) wcols += p->w[i];
-    logf(1,
+    log_line(1,
          "plan %p: %d x %d, J = %d, eta = %d, %s %s shearlets, aux order %d, %s finest scale; window columns %lld "
          "of %lld, spectrum hull values %zu, plane groups %d; device bytes held by the library %zu",
          (void*)p, M, N, J, p->eta, o.complex_shearlets ? "complex" : "real",
@@ -912,7 +912,7 @@ int ffst_forward(const ffst_plan* p, const float* f, float* coeffs, int batch, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   if (!t_tuning_calls)
-    logf(2, "plan %p ffst_forward: %d image(s), %d per unit, %d line(s) per column", (const void*)p, batch,
+    log_line(2, "plan %p ffst_forward: %d image(s), %d per unit, %d line(s) per column", (const void*)p, batch,
          sc.chunk_imgs, sc.fwd_nparts);
   float2* F = static_cast<float2*>(ws);
   float2* Y = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
@@ -984,7 +984,7 @@ int adjoint_real(const ffst_plan* p, const float* coeffs, float* f, int batch, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Schedule sc = schedule(p, batch);
   if (!t_tuning_calls)
-    logf(2, "plan %p %s: %d image(s), %d per unit, %d line(s) per column (%s)", (const void*)p, what, batch,
+    log_line(2, "plan %p %s: %d image(s), %d per unit, %d line(s) per column (%s)", (const void*)p, what, batch,
          sc.chunk_imgs, sc.nparts, sc.fused ? "inverse FFT in the column pass" : "partial sums");
   float2* A = static_cast<float2*>(ws);
   float2* Z = reinterpret_cast<float2*>(static_cast<char*>(ws) + sc.fa_bytes);
@@ -1164,7 +1164,7 @@ int ffst_set_tuning_ex(ffst_plan* p, const ffst_tuning* t) {
   p->tune_blocks_per_cu = t->blocks_per_cu;
   p->tune_col_values = t->col_values == col_values(p->M) ? 0 : t->col_values;
   p->tune_row_block = t->row_block == 2 ? 2 : 0;
-  logf(1, "plan %p tuning: nparts %d, fwd_nparts %d, blocks per CU %d, col_values %d, row_block %d", (void*)p,
+  log_line(1, "plan %p tuning: nparts %d, fwd_nparts %d, blocks per CU %d, col_values %d, row_block %d", (void*)p,
        t->nparts, t->fwd_nparts, t->blocks_per_cu, t->col_values, t->row_block);
   return ok();
 }
@@ -1282,7 +1282,7 @@ int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch
   }
   apply(best_t);
   if (best_ms) *best_ms = best;
-  logf(1,
+  log_line(1,
        "plan %p tuned for %d image(s): nparts %d, fwd_nparts %d, blocks per CU %d, col_values %d, row_block %d; "
        "forward + adjoint %.4f ms",
        (void*)p, batch, best_t.nparts, best_t.fwd_nparts, best_t.blocks_per_cu,
@@ -1292,7 +1292,7 @@ int ffst_tune(ffst_plan* p, const float* f, float* coeffs, float* out, int batch
 
 void ffst_destroy(ffst_plan* p) {
   if (!plan_ok(p)) return;
-  logf(1, "plan %p destroyed", (void*)p);
+  log_line(1, "plan %p destroyed", (void*)p);
   (void)hipDeviceSynchronize();
   free_plan(p);
 }

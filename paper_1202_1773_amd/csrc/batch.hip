@@ -308,12 +308,12 @@ int ffst_batch_create(int count, const int* M, const int* N, const int* J, const
     return fail(FFST_EDEVICE, "stream/event creation: %s", hipGetErrorString(e));
   }
   *out = b;
-  logf(1, "batch %p: %d image(s) in %zu size class(es), %lld coefficients, workspace %zu bytes", (void*)b, count, nc,
+  log_line(1, "batch %p: %d image(s) in %zu size class(es), %lld coefficients, workspace %zu bytes", (void*)b, count, nc,
        (long long)b->coef_total, b->ws_total);
   for (size_t c = 0; c < nc; ++c) {
     int cm = 0, cn = 0, cj = 0;
     (void)ffst_plan_info(b->plans[c], &cm, &cn, &cj, nullptr);
-    logf(1, "batch %p class %zu: %d image(s) of %d x %d, J = %d, plan %p", (void*)b, c, b->cls_images[c], cm, cn, cj,
+    log_line(1, "batch %p class %zu: %d image(s) of %d x %d, J = %d, plan %p", (void*)b, c, b->cls_images[c], cm, cn, cj,
          (void*)b->plans[c]);
   }
   return FFST_OK;
@@ -380,14 +380,14 @@ int ffst_batch_tune(ffst_batch* b, const float* f, float* coeffs, float* out, vo
     drop_graphs(b);
   }
   if (st == FFST_OK)
-    logf(1, "batch %p tuned: %.4f ms before, %.4f ms with the classes' own settings; %s", (void*)b, before, after,
+    log_line(1, "batch %p tuned: %.4f ms before, %.4f ms with the classes' own settings; %s", (void*)b, before, after,
          after > before ? "kept the previous settings" : "kept the tuned settings");
   return st;
 }
 
 void ffst_batch_destroy(ffst_batch* b) {
   if (!batch_ok(b)) return;
-  logf(1, "batch %p destroyed", (void*)b);
+  log_line(1, "batch %p destroyed", (void*)b);
   (void)hipDeviceSynchronize();
   free_batch(b);
 }

@@ -206,7 +206,7 @@ int fail(int status, const char* fmt, ...);
 // every transform call; "<level>:<path>" or a bare path (level 1) appends to
 // that file instead of stderr. Lines are written whole, under a lock.
 int log_level();
-void logf(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void log_line(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // roctx range over a scope (shown on rocprofv3 --marker-trace timelines;
 // nearly free when no profiler is attached). `name` must outlive the scope.

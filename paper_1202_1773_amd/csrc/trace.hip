@@ -53,7 +53,7 @@ LogSink& sink() {
 
 int ffst::log_level() { return sink().level; }
 
-void ffst::logf(int level, const char* fmt, ...) {
+void ffst::log_line(int level, const char* fmt, ...) {
   LogSink& k = sink();
   if (level > k.level || !k.fp) return;
   char buf[1024];
