@@ -252,7 +252,8 @@ int ffst_get_tuning(const ffst_plan* plan, int* nparts, int* blocks_per_cu);
 /*
  * All launch settings of a plan, including the kernel shapes compiled in
  * more than one form (real-shearlet passes; the complex shearlets' own column
- * kernels always take the defaults):
+ * kernels always take the default col_values, and follow nparts and
+ * fwd_nparts):
  *   col_values  values per lane of the column-direction FFTs: 0 = the default
  *               for the column length M (8 below 1024, 16 from 1024 on for
  *               powers of two; 12 for 3 * 2^k), or the alternative compiled for
@@ -291,7 +292,8 @@ int ffst_get_tuning_ex(const ffst_plan* plan, ffst_tuning* tuning);
  * fwd_nparts in {1, 2, 4, 8} with it and keeps the fastest of those. coeffs (the
  * coefficient buffer for the plan's kind, as for the transform calls) and
  * out ([batch][M][N]) are scratch. Synchronous. *best_ms (may be NULL)
- * receives the fastest time of one forward + adjoint. The tuning calls change
+ * receives the time of one forward + adjoint with the settings kept (best of
+ * 3 runs after a warm-up). The tuning calls change
  * the plan: no other call may use the plan while they run.
  */
 int ffst_tune(ffst_plan* plan, const float* f, float* coeffs, float* out, int batch, void* ws,
