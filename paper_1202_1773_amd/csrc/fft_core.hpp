@@ -160,6 +160,39 @@ struct Dft<16, INV> {
   }
 };
 
+// 32 = 2 x 16: DFT16 of the even and the odd elements, twiddles
+// exp(-+ 2 pi i k / 32), k < 16.
+template <bool INV>
+struct Dft<32, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 e[16], o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      e[k] = a[2 * k];
+      o[k] = a[2 * k + 1];
+    }
+    Dft<16, INV>::run(e);
+    Dft<16, INV>::run(o);
+    // cos(k pi / 16), k = 0 .. 8
+    constexpr float c[9] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f, 0.83146961230254523708f,
+                            0.70710678118654752440f, 0.55557023301960222474f, 0.38268343236508977173f,
+                            0.19509032201612826785f, 0.0f};
+    constexpr float sg = INV ? 1.0f : -1.0f;
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+      // exp(-+ i k pi / 16) = (cos, -+ sin), sin(k pi/16) = cos((8 - k) pi/16)
+      const float ck = k <= 8 ? c[k] : -c[16 - k];
+      const float sk = k <= 8 ? c[8 - k] : c[k - 8];
+      o[k] = cmul(o[k], make_float2(ck, sg * sk));
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      a[k] = cadd(e[k], o[k]);
+      a[k + 16] = csub(e[k], o[k]);
+    }
+  }
+};
+
 // 6 = 2 x 3: DFT3 of the even and the odd elements, twiddles exp(-+ 2 pi i k / 6).
 template <bool INV>
 struct Dft<6, INV> {
