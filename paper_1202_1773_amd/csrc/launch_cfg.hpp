@@ -119,14 +119,16 @@ __host__ __device__ constexpr int alt_block_rows(int GS) {
 }
 
 // Real rows of length N = 2L (complex FFT of length L), RB rows per block
-// (RBM = 2: the alternative height). Rows of 2048 points take 32 values per
-// lane (radix 32 x 32): 32 lanes per row, so a 512-thread block holds 16 rows
-// and writes 128-byte column segments (with 16 values: 8 rows, 64 bytes;
-// measured 0.73 -> 0.65 ms for the inverse row pass of a 2048 x 2048 image).
-// Longer rows would spill with 32 values.
+// (RBM = 2: the alternative height). Rows of 1024 and 2048 points take 32
+// values per lane. 2048 (radix 32 x 32): 32 lanes per row, so a 512-thread
+// block holds 16 rows and writes 128-byte column segments (with 16 values:
+// 8 rows, 64 bytes; measured 0.73 -> 0.65 ms for the inverse row pass of a
+// 2048 x 2048 image). 1024 (radix 32 x 16): one LDS exchange instead of two
+// (16 x 16 x 2) and 256-thread blocks of 16 rows (the 64-image uneven batch:
+// 6.15 -> 5.94 ms). Longer rows would spill with 32 values.
 template <int L, int RBM = 1>
 struct RowCfg {
-  static constexpr int V = L == 1024 ? 32 : line_values(L);
+  static constexpr int V = (L == 512 || L == 1024) ? 32 : line_values(L);
   static constexpr int G = L / V;                      // lanes per row
   static constexpr int GS = group_slots(G);            // lane slots per row
   static constexpr int SYNC = GS <= 64 ? kWave : kBlock;
